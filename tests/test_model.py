@@ -1,0 +1,205 @@
+"""Pins of the oracle's order model (the paper's steps applied in the GPU
+library's documented reduction order).
+
+* With the data confined to one lane's chain, the model must equal the
+  paper's sequential loop bitwise (every other chain, lane, wave and block
+  contributes (+0, +0), and combining with a zero pair is exact).
+* Combines are exact (Theorem 2): on exact-grid data value + error equals
+  the exact sum for every launch shape and both forms.
+* Rigorous results satisfy |v + e - S| <= 4 N u^2 sum|x y|.
+* The twofold value equals the plain value of the same order.
+* A one-tile segment is a single-vector reduction with one 64-lane block.
+"""
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+LAUNCHES = [(256, 1, 1), (256, 4, 3), (512, 2, 2), (1024, 8, 5), (64, 1, 1), (128, 2, 7)]
+
+
+def _u(dtype):
+    return 2.0 ** -(np.finfo(dtype).nmant + 1)
+
+
+def _seq_kind(mode, is_dot):
+    if mode == "plain":
+        return "dot" if is_dot else "sum"
+    if mode == "fast":
+        return "dottf" if is_dot else "sumtf"
+    return "dott" if is_dot else "sumt"
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("mode", ["plain", "fast", "rigorous"])
+@pytest.mark.parametrize("is_dot", [False, True])
+def test_single_lane_reduces_to_sequential(dtype, mode, is_dot):
+    W = 16 // np.dtype(dtype).itemsize
+    bt, U, gb = 256, 2, 3
+    L = bt * gb
+    rng = np.random.default_rng(21)
+    for mis in range(W):
+        head = (W - mis) % W
+        nvec = 37 * U * L + 5  # several rounds and a partial one
+        n = head + nvec * W + (W - 1 if W > 1 else 0)
+        r = n - head - nvec * W
+        # lane 0, chain 0: head element 0 (if any), vectors k = q*U*L + u*L,
+        # tail element 0 (if any)
+        idx = []
+        if head:
+            idx.append(0)
+        for k in range(0, nvec, L):
+            idx.append(head + k * W)
+        if r:
+            idx.append(head + nvec * W)
+        x = np.zeros(n, dtype=dtype)
+        vals = (rng.standard_normal(len(idx)) * np.exp2(rng.integers(-8, 8, len(idx)))).astype(dtype)
+        x[idx] = vals
+        y = None
+        yv = None
+        if is_dot:
+            y = rng.standard_normal(n).astype(dtype)
+            yv = y[idx]
+        got = oracle.model_single(mode, x, y, x_misalign=mis, block_threads=bt, unroll=U,
+                                  grid_blocks=gb)
+        v, e = oracle.seq(_seq_kind(mode, is_dot), vals, yv)
+        assert got[0] == float(v) and got[1] == float(e), (mis, got, v, e)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("mode", ["fast", "rigorous"])
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_exact_grid_all_launches(dtype, mode, launch):
+    bt, U, gb = launch
+    for n in (0, 1, 7, 1000, 65536 + 3):
+        x = synth.uniform(n + 17, n, dtype)
+        ex = oracle.Exact(x)
+        for mis in (0, 16 // np.dtype(dtype).itemsize - 1):
+            got = oracle.model_single(mode, x, None, mis, bt, U, gb)
+            assert ex.diff(got[0], got[1]) == 0.0, (n, mis, got)
+            plain = oracle.model_single("plain", x, None, mis, bt, U, gb)
+            assert plain[0] == got[0] and plain[1] == 0.0
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_rigorous_dot_bound_all_launches(dtype, launch):
+    bt, U, gb = launch
+    u = _u(dtype)
+    for seed, n in ((1, 4099), (2, 1 << 16)):
+        x, y = synth.uniform(seed, n, dtype, count=2)
+        ex = oracle.Exact(x, y)
+        got = oracle.model_single("rigorous", x, y, 0, bt, U, gb)
+        assert abs(ex.diff(got[0], got[1])) <= 4 * n * u * u * ex.A
+        plain = oracle.model_single("plain", x, y, 0, bt, U, gb)
+        assert plain[0] == got[0]
+        fast = oracle.model_single("fast", x, y, 0, bt, U, gb)
+        assert fast[0] == got[0]
+
+
+def test_illconditioned_rigorous_bound_model():
+    for dtype in (np.float32, np.float64):
+        u = _u(dtype)
+        x, y = synth.illcond_dot(synth.illcond_seed(16), 1 << 16, 1e16, dtype)
+        ex = oracle.Exact(x, y)
+        got = oracle.model_single("rigorous", x, y, 0, 256, 4, 16)
+        assert abs(ex.diff(got[0], got[1])) <= 4 * x.size * u * u * ex.A
+
+
+def test_two_lanes_combine_exact():
+    """Data only on lanes 0 and 1 (chain 0, first vector each): the result is
+    the exact combine of two one-element chains."""
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        a, b = rng.standard_normal(2) * np.exp2(rng.integers(-30, 30, 2))
+        x = np.zeros(2 * 256 * 2, dtype=np.float64)
+        x[0], x[2] = a, b  # vector 0 -> lane 0, vector 1 -> lane 1
+        got = oracle.model_single("rigorous", x, None, 0, 256, 1, 1)
+        assert F(got[0]) + F(got[1]) == F(a) + F(b)
+        assert got[0] == a + b
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_tiny_sizes(dtype):
+    assert list(oracle.model_single("rigorous", np.zeros(0, dtype))) == [0.0, 0.0]
+    x = np.array([0.3], dtype=dtype)
+    y = np.array([-0.7], dtype=dtype)
+    got = oracle.model_single("rigorous", x)
+    assert got[0] == float(x[0]) and got[1] == 0.0
+    got = oracle.model_single("rigorous", x, y)
+    p = (x * y)[0]
+    assert got[0] == float(p)
+    assert F(got[0]) + F(got[1]) == F(float(x[0])) * F(float(y[0]))
+
+
+def test_wide_mode_matches_binary64_sum_of_widened():
+    x, y = synth.uniform(8, 10000, np.float32, count=2)
+    got = oracle.model_single("wide", x, None, 0, 256, 1, 1)
+    ex = oracle.Exact(x)
+    # binary64 sums of binary32 values with |x| < 1 and n < 2^29 are exact
+    assert got[0] == ex.S and got[1] == 0.0
+    got = oracle.model_single("wide", x, y, 0, 256, 1, 1)
+    assert abs(got[0] - oracle.Exact(x, y).S) <= 1e-13
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("mode", ["plain", "fast", "rigorous"])
+def test_one_tile_segment_is_single_block_of_64(dtype, mode):
+    W = 16 // np.dtype(dtype).itemsize
+    ts = 64 * W * 8
+    rng = np.random.default_rng(3)
+    for n in (1, 5, ts - 1, ts):
+        for mis in range(W):
+            x = rng.standard_normal(n).astype(dtype)
+            y = rng.standard_normal(n).astype(dtype)
+            seg = oracle.model_seg(mode, x, [0, n], y, x_misalign=mis, unroll=2, tile_elems=ts)
+            one = oracle.model_single(mode, x, y, mis, 64, 2, 1)
+            assert seg[0][0] == one[0] and seg[0][1] == one[1]
+
+
+def test_segments_are_independent():
+    rng = np.random.default_rng(9)
+    lengths = [0, 1, 300, 1024, 1025, 5000, 0, 77]
+    off = synth.offsets_from_lengths(lengths)
+    x = rng.standard_normal(off[-1])
+    y = rng.standard_normal(off[-1])
+    ts = 1024
+    allseg = oracle.model_seg("rigorous", x, off, y, 0, 4, ts)
+    for s in range(len(lengths)):
+        a, b = off[s], off[s + 1]
+        # the segment alone, at the same alignment (a mod 2 elements)
+        one = oracle.model_seg("rigorous", x[a:b], [0, b - a], y[a:b], int(a % 2), 4, ts)
+        assert allseg[s][0] == one[0][0] and allseg[s][1] == one[0][1]
+    assert list(allseg[0]) == [0.0, 0.0] and list(allseg[6]) == [0.0, 0.0]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_segmented_exact_grid_and_bound(dtype):
+    W = 16 // np.dtype(dtype).itemsize
+    ts = 64 * W * 4
+    lengths = synth.segment_lengths(3, 60, max_len=1 << 14)
+    off = synth.offsets_from_lengths(lengths)
+    x, y = synth.uniform(31, int(off[-1]), dtype, count=2)
+    got = oracle.model_seg("rigorous", x, off, None, 0, 4, ts)
+    gotd = oracle.model_seg("rigorous", x, off, y, 0, 4, ts)
+    u = _u(dtype)
+    for s in range(len(lengths)):
+        a, b = off[s], off[s + 1]
+        assert oracle.Exact(x[a:b]).diff(*got[s]) == 0.0
+        ex = oracle.Exact(x[a:b], y[a:b])
+        assert abs(ex.diff(*gotd[s])) <= 4 * (b - a) * u * u * ex.A
+
+
+def test_model_rejects_bad_arguments():
+    x = np.zeros(10)
+    with pytest.raises(ValueError):
+        oracle.model_single("rigorous", x, None, 0, 100, 1, 1)
+    with pytest.raises(ValueError):
+        oracle.model_single("wide", x, None, 0, 256, 1, 1)
+    with pytest.raises(ValueError):
+        oracle.model_seg("rigorous", x, [0, 5, 3], None, 0, 1, 128)
+    with pytest.raises(ValueError):
+        oracle.model_seg("rigorous", x, [0, 10], None, 0, 1, 100)
