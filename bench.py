@@ -1,0 +1,189 @@
+"""Benchmark: twofold dot products of ill-conditioned vectors on one GPU.
+
+Workload (one step): the fast and the rigorous twofold dot of 12 resident
+vector pairs of N = 2^24 elements, binary32 and binary64, generated with
+target conditions 1e6, 1e8, ..., 1e16 (synth.illcond_dot). All rigorous
+dots run first, then all fast ones, so no pair is re-read while it could
+still sit in the 256 MB last-level cache. Prints one JSON line.
+
+The dominant kernel is the binary64 rigorous dot (256 MiB per launch); its
+average duration is measured with HIP events on the launch stream during
+the timed steps and gives the roofline entry (algorithmic bytes / time vs
+8 TB/s). The CPU-baseline leg, the only part that runs the oracle, times
+the oracle's sequential paper-order loops on one host thread over the same
+inputs and grades every form's GPU result against the exact sum.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "twofold dot/sum Gelem/s & %HBM peak; FP32-twofold vs FP64-plain at equal err"
+HBM_PEAK_GBS = 8000.0
+N = 1 << 24
+DECADES = (6, 8, 10, 12, 14, 16)
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_inputs():
+    import numpy as np
+    import synth
+
+    jobs = [(dt, d) for dt in (np.float32, np.float64) for d in DECADES]
+
+    def one(job):
+        dt, d = job
+        return job, synth.illcond_dot(synth.illcond_seed(d), N, 10.0 ** d, dt)
+
+    with ThreadPoolExecutor(max_workers=min(12, os.cpu_count() or 4)) as ex:
+        return dict(ex.map(one, jobs))
+
+
+def gpu_results(dev_in, tf):
+    """Every form's pair for every input (outside the timed region)."""
+    import numpy as np
+
+    res = {}
+    for k, (xd, yd) in dev_in.items():
+        for mode in ("plain", "fast", "rigorous"):
+            res[k + (mode,)] = tf.dot(xd, yd, mode).double().cpu().numpy()
+        if k[0] == np.float32:
+            res[k + ("dotd",)] = tf.dotd(xd, yd).cpu().numpy()
+    return res
+
+
+def oracle_leg(host, gpu):
+    """The CPU-baseline leg, the only part of the benchmark that runs the
+    oracle: (1) times the oracle's sequential rigorous and fast twofold dots
+    (paper order, FMA remainder) over every input of one step on one host
+    thread; (2) grades the GPU's pairs against the exact accumulator:
+    |v + e - S| / sum|x y|, median over the conditions."""
+    import numpy as np
+
+    import oracle
+
+    t0 = time.perf_counter()
+    elems = 0
+    for (dt, d), (x, y) in host.items():
+        oracle.seq("dott", x, y)
+        oracle.seq("dottf", x, y)
+        elems += 2 * x.size
+    dt_s = time.perf_counter() - t0
+    base = {"value": round(elems / dt_s / 1e9, 4), "unit": "Gelem/s", "cores": 1, "kind": "oracle",
+            "sample": "one full step: sequential rigorous + fast twofold dot (paper order, FMA "
+                      "remainder) over the 12 ill-conditioned pairs, N=2^24 each, %.1f s" % dt_s}
+    rows = {}
+    for (dt, d), (x, y) in host.items():
+        ex = oracle.Exact(x, y)
+        key = "f32" if dt == np.float32 else "f64"
+        for mode in ("plain", "fast", "rigorous"):
+            p = gpu[(dt, d, mode)]
+            rows.setdefault("%s_%s" % (key, mode), []).append(abs(ex.diff(p[0], p[1])) / ex.A)
+        if dt == np.float32:
+            p = gpu[(dt, d, "dotd")]
+            rows.setdefault("f32data_f64plain", []).append(abs(ex.diff(p[0])) / ex.A)
+        rows.setdefault("cond_" + key, []).append(2 * ex.A / abs(ex.S) if ex.S else float("inf"))
+    acc = {"measure": "median over conditions of |v + e - S| / sum|x y|"}
+    for k, v in rows.items():
+        acc[k] = ["%.3g" % c for c in v] if k.startswith("cond_") else float("%.3g" % np.median(v))
+    return base, acc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this library's reduction runs on one device "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1401_0248_amd as tf
+
+    dev = torch.device("cuda:0")
+    log("generating 12 ill-conditioned pairs, N=2^24")
+    t0 = time.perf_counter()
+    host = make_inputs()
+    log("inputs ready in %.1f s; copying to the GPU" % (time.perf_counter() - t0))
+    dev_in = {k: (torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev))
+              for k, (x, y) in host.items()}
+    order = sorted(dev_in.keys(), key=lambda k: (k[0] == np.float32, k[1]))
+    outs = {k: torch.empty(2, dtype=dev_in[k][0].dtype, device=dev) for k in dev_in}
+    ws_bytes = max(tf._lib.load().twofold_workspace_bytes_single(8, 1, 2, N, None),
+                   tf._lib.load().twofold_workspace_bytes_single(4, 1, 2, N, None))
+    ws = tf.workspace(ws_bytes, dev)
+    stream = torch.cuda.current_stream(dev)
+    dominant = [k for k in order if k[0] == np.float64]
+    ev = []
+
+    def step(timed):
+        for mode in ("rigorous", "fast"):
+            for k in order:
+                xd, yd = dev_in[k]
+                mark = timed and mode == "rigorous" and k in dominant
+                if mark:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                tf.dot(xd, yd, mode, out=outs[k], ws=ws)
+                if mark:
+                    e1.record(stream)
+                    ev.append((e0, e1))
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log("timing %d steps" % args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    elems_step = 2 * len(order) * N
+    value = elems_step * args.steps / elapsed / 1e9
+    durs = [a.elapsed_time(b) * 1e-3 for a, b in ev]
+    avg = sum(durs) / len(durs)
+    bytes_launch = 2 * N * 8  # x and y, binary64
+    achieved = bytes_launch / avg / 1e9
+    log("step %.3f ms, %.1f Gelem/s; f64 rigorous dot %.1f us avg, %.0f GB/s"
+        % (ms_step, value, avg * 1e6, achieved))
+
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Gelem/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "ill-conditioned twofold dot, fast+rigorous, f32 and f64, "
+                               "N=2^24, target cond 1e6..1e16 (12 pairs)",
+                   "n": N, "pairs": len(order), "dots_per_step": 2 * len(order),
+                   "launch": "tuned default"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "single_kernel<double, rigorous, dot>",
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg * 1e6, 2)},
+    }
+    if not args.no_cpu_baseline:
+        gpu = gpu_results(dev_in, tf)
+        log("cpu baseline leg: oracle timing and grading")
+        res["cpu_baseline"], res["accuracy"] = oracle_leg(host, gpu)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * twofold.h: C interface of the gfx950 twofold summation library.
+ *
+ * Twofold summation (E. Latkin, "Twofold fast summation", 2013) returns a sum
+ * sum x_n or a dot product sum x_n*y_n as a pair (value, error): value is
+ * what plain floating-point summation computes, and error collects the
+ * round-offs that summation made, so that value + error approximates the
+ * exact result better than value alone ("Overview"; section "Algorithms",
+ * the text after Example 2).
+ *
+ * Modes (section "Algorithms"):
+ *   TWOFOLD_PLAIN     direct summation (Example 3, second function); error 0.
+ *   TWOFOLD_FAST      fast twofold step built on Dekker's fast-two-sum
+ *                     (Theorem 1, Example 1). Exact per step only when
+ *                     |running sum| >= |item|; otherwise the step loses part
+ *                     of its round-off (at most about u*|item|).
+ *   TWOFOLD_RIGOROUS  rigorous twofold step built on Knuth's two-sum
+ *                     (Theorem 2, Example 3): every step's round-off is
+ *                     captured exactly.
+ * Dot products: the paper substitutes the rounded product a[i]*b[i] for the
+ * data item (end of "Algorithms"). This library also captures the product's
+ * rounding: p = fl(x*y), pi = fma(x, y, -p), x*y = p + pi exactly unless the
+ * product underflows; p is the item and pi joins the error
+ * (fast: e += pi - c; rigorous: e += (ds + dy) + pi).
+ * The paper's sumd/dotd (binary32 data, binary64 accumulator, section
+ * "Performance", function list) are twofold_sumd_f32 / twofold_dotd_f32.
+ *
+ * All arithmetic is IEEE round-to-nearest-even with no contraction other
+ * than the one FMA above; binary32 subnormals are kept. A twofold value is
+ * bitwise the plain result of the same launch configuration.
+ *
+ * ---- Reduction order (normative: it fixes every bit of every result) -----
+ * T is float or double, W = 16/sizeof(T) (elements per 16-byte vector).
+ * Every chain starts at (+0, +0). combine((s1,e1),(s2,e2)) is two-sum
+ * (Theorem 2, all six operations) of s1, s2 giving (x, y), then
+ * error (e1 + e2) + y, value x; in plain mode it is (s1 + s2, +0).
+ * Single vector, launch (block_threads BT, unroll U, grid_blocks GB),
+ * L = GB*BT lanes, lane g = block*BT + thread:
+ *   1. head: the h = min(n, elements before x's first 16-byte boundary)
+ *      first elements, element i on lane i, chain 0;
+ *   2. body: V = floor((n-h)/W) vectors; round q gives lane g the vectors
+ *      k = q*U*L + u*L + g, u = 0..U-1 in order (k < V), component j of
+ *      vector k (element h + k*W + j) on chain j;
+ *   3. tail: the r = n - h - V*W last elements, element i of them on lane
+ *      i, chain 0;
+ *   4. each lane combines its chains in order 0, 1, ..., W-1;
+ *   5. each 64-lane wave: for d = 1, 2, 4, 8, 16, 32, lane l replaces its
+ *      pair P_l by combine(P_l, P_{l xor d}) (pairs as before the step);
+ *   6. each block combines its waves' lane-0 pairs in wave order;
+ *   7. if GB = 1 the block pair is the result R; otherwise R is computed in
+ *      binary64 from the GB block pairs (widened exactly): 256 lanes, lane
+ *      l starting at (+0,+0) and combining pairs l, l+256, ... in order,
+ *      then steps 5 and 6 over those 256 lanes;
+ *   8. finalize R = (V, E): binary64 results are (V, E); binary32 results
+ *      are value fl32(V) and error fl32((V - value) + E), in binary64
+ *      (V - value is exact); plain binary32 has error +0.
+ * Segmented, launch (block_threads, unroll U, grid_blocks, tile_elems TS):
+ *   segment s covers elements [off[s], off[s+1]) and has ceil(len/TS)
+ *   tiles; tile j covers [off[s] + j*TS, min(off[s+1], off[s] + (j+1)*TS));
+ *   each tile is reduced by one 64-lane wave with steps 1-5 applied to the
+ *   tile's range (L = 64); a one-tile segment's pair is finalized (step 8);
+ *   the tile pairs of a longer segment are combined in binary64 by 64
+ *   lanes, lane l starting at (+0,+0) and combining tiles l, l+64, ... in
+ *   tile order, then step 5, then step 8; an empty segment gives (+0,+0).
+ *   Which wave handles which tile does not change the result.
+ * Wide (sumd/dotd): as above with binary64 chains over widened binary32
+ * data and the plain combine; results are binary64 pairs with error +0.
+ *
+ * ---- Conventions --------------------------------------------------------
+ * Pointers: x, y, out, offsets and ws are device pointers (hipMalloc or
+ * torch device memory) on the current HIP device; the caller owns them.
+ * Data pointers must be aligned to their element size (they may be NULL
+ * when there are no elements); x and y may have different alignments within
+ * a 16-byte line. stream is a hipStream_t
+ * (NULL: the legacy default stream). Calls are asynchronous: results are in
+ * out once the stream reaches them. The execute paths never allocate, free
+ * or synchronise, and may be captured into a HIP graph.
+ * Workspace: ws must hold at least the bytes the matching
+ * twofold_workspace_bytes_* call returns and must have been prepared once
+ * by twofold_workspace_init; every call leaves it prepared. One workspace
+ * must not be used by two calls that may run at the same time.
+ * Status: 0 on success, a negative TWOFOLD_E* code otherwise; arguments are
+ * checked on the host before any HIP call, and nothing is launched on
+ * error. Non-finite inputs give IEEE values and an unspecified error.
+ */
+#ifndef TWOFOLD_H
+#define TWOFOLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The pair type of the paper's Example 1 (struct twofold<number>). */
+typedef struct { float value, error; } twofold_f32_t;
+typedef struct { double value, error; } twofold_f64_t;
+
+enum {
+  TWOFOLD_PLAIN = 0,
+  TWOFOLD_FAST = 1,
+  TWOFOLD_RIGOROUS = 2,
+  TWOFOLD_WIDE = 3 /* binary32 data, binary64 accumulator (segmented plans) */
+};
+
+enum {
+  TWOFOLD_OK = 0,
+  TWOFOLD_EINVAL = -1,     /* bad pointer, size, mode or launch value    */
+  TWOFOLD_EWORKSPACE = -2, /* workspace missing or too small             */
+  TWOFOLD_EHIP = -3,       /* a HIP call failed (launch or runtime)      */
+  TWOFOLD_EALIGN = -4,     /* a data pointer is not element-aligned      */
+  TWOFOLD_EOFFSETS = -5    /* segment offsets not non-decreasing from 0.. */
+};
+
+/* Launch configuration. Zero fields take the tuned default.
+ *   block_threads: threads per block, 256, 512 or 1024 (single vector);
+ *                  64..1024 in steps of 64 (segmented).
+ *   unroll:        vectors per lane per round: 1, 2, 4 or 8.
+ *   grid_blocks:   single vector: exactly this many blocks, 1..1048576;
+ *                  segmented: persistent blocks, 1..1048576.
+ *   tile_elems:    segmented only: tile length, a positive multiple of
+ *                  64*16/sizeof(T), at most 2^30.                        */
+typedef struct {
+  int32_t block_threads;
+  int32_t unroll;
+  int32_t grid_blocks;
+  int32_t reserved; /* must be 0 */
+  int64_t tile_elems;
+} twofold_launch_t;
+
+/* Fill *out with the configuration a call with launch == NULL uses:
+ * kind 0 single vector (n elements), 1 segmented (n total elements,
+ * nseg segments). dtype 4 or 8; mode TWOFOLD_*. */
+int twofold_default_launch(int kind, int dtype, int is_dot, int mode, int64_t n, int64_t nseg,
+                           twofold_launch_t* out);
+
+/* Workspace size for a single-vector call, and for a segmented call with
+ * nseg segments over n_total elements. launch NULL: the default. */
+size_t twofold_workspace_bytes_single(int dtype, int is_dot, int mode, int64_t n,
+                                      const twofold_launch_t* launch);
+size_t twofold_workspace_bytes_seg(int dtype, int is_dot, int mode, int64_t n_total, int64_t nseg,
+                                   const twofold_launch_t* launch);
+/* Prepare a workspace (zero it and stamp its header) on stream. */
+int twofold_workspace_init(void* ws, size_t ws_bytes, void* stream);
+
+/* ---- single vector: one (value, error) pair into *out (device) ---------
+ * Section "Algorithms": sumtf (Example 1), sumt and sum (Example 3), dot by
+ * substitution of x[i]*y[i]; mode selects the form. n >= 0; n = 0 gives
+ * (+0, +0). */
+int twofold_sum_f32(const float* x, int64_t n, int mode, const twofold_launch_t* launch,
+                    twofold_f32_t* out, void* ws, size_t ws_bytes, void* stream);
+int twofold_sum_f64(const double* x, int64_t n, int mode, const twofold_launch_t* launch,
+                    twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
+int twofold_dot_f32(const float* x, const float* y, int64_t n, int mode,
+                    const twofold_launch_t* launch, twofold_f32_t* out, void* ws, size_t ws_bytes,
+                    void* stream);
+int twofold_dot_f64(const double* x, const double* y, int64_t n, int mode,
+                    const twofold_launch_t* launch, twofold_f64_t* out, void* ws, size_t ws_bytes,
+                    void* stream);
+/* Paper's sumd / dotd: binary32 data summed into binary64 (products of two
+ * binary32 numbers are exact in binary64). out->error is +0. */
+int twofold_sumd_f32(const float* x, int64_t n, const twofold_launch_t* launch,
+                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
+int twofold_dotd_f32(const float* x, const float* y, int64_t n, const twofold_launch_t* launch,
+                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- segmented (CSR) batches: nseg pairs into out[0..nseg) ---------------
+ * offsets: device int64[nseg + 1], non-decreasing, offsets[0] >= 0 and
+ * offsets[nseg] <= n_total (the length of x and y). Checked on the device:
+ * on violation every out[s] is NaN. Two kernels (tiling, then reduction).
+ * mode TWOFOLD_WIDE is not accepted here (see the plan interface). */
+int twofold_segsum_f32(const float* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
+                       int mode, const twofold_launch_t* launch, twofold_f32_t* out, void* ws,
+                       size_t ws_bytes, void* stream);
+int twofold_segsum_f64(const double* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
+                       int mode, const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                       size_t ws_bytes, void* stream);
+int twofold_segdot_f32(const float* x, const float* y, int64_t n_total, const int64_t* offsets,
+                       int64_t nseg, int mode, const twofold_launch_t* launch, twofold_f32_t* out,
+                       void* ws, size_t ws_bytes, void* stream);
+int twofold_segdot_f64(const double* x, const double* y, int64_t n_total, const int64_t* offsets,
+                       int64_t nseg, int mode, const twofold_launch_t* launch, twofold_f64_t* out,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* ---- segmented plans: host offsets fixed once, one kernel per execute ---
+ * create: validates offsets_host (host int64[nseg+1], offsets[0] = 0,
+ * non-decreasing), builds the tile table and copies offsets and table to
+ * device memory owned by the plan, with the plan's per-segment completion
+ * counters (synchronous; not capturable). The workspace of an execute
+ * holds only the tile pairs.
+ * dtype 4 or 8; mode TWOFOLD_* (WIDE only with dtype 4).
+ * execute: one persistent kernel on stream; out is twofold_f32_t[nseg] for
+ * dtype 4 modes PLAIN/FAST/RIGOROUS, twofold_f64_t[nseg] otherwise; y must
+ * be NULL for sums and given for dots (is_dot at creation). Capturable.
+ * A plan must not execute on two streams at once. */
+typedef struct twofold_seg_plan twofold_seg_plan_t;
+int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype, int is_dot,
+                            int mode, const twofold_launch_t* launch, twofold_seg_plan_t** plan);
+size_t twofold_seg_plan_workspace_bytes(const twofold_seg_plan_t* plan);
+int twofold_seg_plan_get_launch(const twofold_seg_plan_t* plan, twofold_launch_t* out);
+int twofold_seg_plan_execute(const twofold_seg_plan_t* plan, const void* x, const void* y,
+                             void* out, void* ws, size_t ws_bytes, void* stream);
+int twofold_seg_plan_destroy(twofold_seg_plan_t* plan);
+
+/* ---- instruments ----------------------------------------------------------
+ * Memory-only probe (the paper's read1/read2, section "Memory reading"):
+ * streams x (and y, if not NULL), nbytes each, with 16-byte loads in the
+ * single-vector lane order of launch (block_threads, unroll, grid_blocks;
+ * every field required), and ORs all loaded bits together. x, y 16-byte
+ * aligned, nbytes a multiple of 16; sink: device uint64[grid_blocks].   */
+int twofold_probe_read(const void* x, const void* y, int64_t nbytes, const twofold_launch_t* launch,
+                       uint64_t* sink, void* stream);
+/* Compute-only probe (the paper's p-functions, section "Purely
+ * computing"): every lane feeds 4*16/dtype register-resident items through
+ * its chains iters times with the step of (dtype, is_dot, mode), 4 rounds
+ * of W items per iteration. seed: device array of 64 elements of dtype;
+ * sink: device double[2 * grid_blocks * block_threads].                 */
+int twofold_probe_compute(int dtype, int is_dot, int mode, const void* seed, int64_t iters,
+                          const twofold_launch_t* launch, double* sink, void* stream);
+
+/* Static string for a status code. */
+const char* twofold_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

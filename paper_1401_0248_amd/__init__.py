@@ -1,0 +1,280 @@
+"""Twofold summation on AMD Instinct MI355X (gfx950).
+
+Python binding of libtwofold.so (include/twofold.h): each function checks
+its tensors, takes the device pointers and torch's current HIP stream, and
+calls the C entry point of the same name. All arithmetic runs in the HIP
+kernels; torch only provides device memory and streams.
+
+Results are device tensors holding (value, error) pairs (E. Latkin,
+"Twofold fast summation": value is the plain floating-point sum, error the
+collected round-offs; section "Algorithms").
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import FAST, PLAIN, RIGOROUS, WIDE, Launch, TwofoldError, check
+
+__all__ = [
+    "sum", "dot", "sumd", "dotd", "segsum", "segdot", "SegPlan", "Launch",
+    "TwofoldError", "workspace", "default_launch", "probe_read", "probe_compute",
+    "PLAIN", "FAST", "RIGOROUS", "WIDE", "mode_id",
+]
+
+_MODES = {"plain": PLAIN, "fast": FAST, "rigorous": RIGOROUS, "wide": WIDE}
+
+
+def mode_id(mode):
+    if isinstance(mode, str):
+        return _MODES[mode]
+    return int(mode)
+
+
+def _launch_ptr(launch):
+    if launch is None:
+        return None
+    if isinstance(launch, dict):
+        launch = Launch(**launch)
+    return ctypes.byref(launch)
+
+
+def _stream_ptr(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_data(*ts):
+    t0 = ts[0]
+    if not t0.is_cuda:
+        raise ValueError("twofold: tensors must be on a GPU device")
+    if t0.dtype not in (torch.float32, torch.float64):
+        raise TypeError("twofold: dtype must be float32 or float64, got %s" % t0.dtype)
+    for t in ts:
+        if t.dim() != 1 or not t.is_contiguous():
+            raise ValueError("twofold: tensors must be 1-D and contiguous")
+        if t.dtype != t0.dtype or t.device != t0.device:
+            raise ValueError("twofold: tensors must share dtype and device")
+    if len(ts) == 2 and ts[0].numel() != ts[1].numel():
+        raise ValueError("twofold: x and y must have the same length")
+
+
+class Workspace:
+    """A prepared device workspace (twofold_workspace_init)."""
+
+    def __init__(self, nbytes, device):
+        nbytes = max(256, int(nbytes))
+        # 256-byte alignment: the caching allocator returns 512-byte blocks.
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        self.ptr = (base + 255) & ~255
+        self.nbytes = nbytes
+        check("twofold_workspace_init",
+              _lib.load().twofold_workspace_init(ctypes.c_void_p(self.ptr), nbytes,
+                                                 _stream_ptr(device)))
+
+
+_ws_cache = {}
+
+
+def workspace(nbytes, device):
+    """The per-(device, stream) workspace, grown to at least nbytes. Calls on
+    one stream run in order, so they can share it."""
+    device = torch.device(device)
+    stream = torch.cuda.current_stream(device).cuda_stream
+    key = (device.index, stream)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.nbytes < nbytes:
+        ws = Workspace(max(nbytes, 2 * ws.nbytes if ws else nbytes), device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def default_launch(kind, dtype, is_dot, mode, n, nseg=0):
+    lc = Launch()
+    check("twofold_default_launch",
+          _lib.load().twofold_default_launch(kind, dtype, int(is_dot), mode_id(mode), n, nseg,
+                                             ctypes.byref(lc)))
+    return lc
+
+
+def _single(fn, x, y, mode, launch, out, ws, out_dtype):
+    L = _lib.load()
+    _check_data(*([x] if y is None else [x, y]))
+    dev = x.device
+    n = x.numel()
+    dt = x.element_size()
+    m = mode_id(mode)
+    lp = _launch_ptr(launch)
+    need = L.twofold_workspace_bytes_single(dt, int(y is not None), m, n, lp)
+    if need == 0:
+        raise TwofoldError("twofold_workspace_bytes_single", _lib.EINVAL)
+    if out is None:
+        out = torch.empty(2, dtype=out_dtype, device=dev)
+    if ws is None:
+        ws = workspace(need, dev)
+    args = [ctypes.c_void_p(x.data_ptr())]
+    if y is not None:
+        args.append(ctypes.c_void_p(y.data_ptr()))
+    args.append(n)
+    if fn not in ("twofold_sumd_f32", "twofold_dotd_f32"):
+        args.append(m)
+    args += [lp, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.ptr), ws.nbytes,
+             _stream_ptr(dev)]
+    check(fn, getattr(L, fn)(*args))
+    return out
+
+
+def sum(x, mode="rigorous", launch=None, out=None, ws=None):  # noqa: A001 (paper's name)
+    """Twofold sum of x: tensor([value, error]) of x's dtype (Example 1 fast,
+    Example 3 rigorous, or plain)."""
+    fn = "twofold_sum_f32" if x.dtype == torch.float32 else "twofold_sum_f64"
+    return _single(fn, x, None, mode, launch, out, ws, x.dtype)
+
+
+def dot(x, y, mode="rigorous", launch=None, out=None, ws=None):
+    """Twofold dot product of x and y: tensor([value, error])."""
+    fn = "twofold_dot_f32" if x.dtype == torch.float32 else "twofold_dot_f64"
+    return _single(fn, x, y, mode, launch, out, ws, x.dtype)
+
+
+def sumd(x, launch=None, out=None, ws=None):
+    """Paper's sumd: float32 data summed in a float64 accumulator."""
+    if x.dtype != torch.float32:
+        raise TypeError("sumd takes float32 data")
+    return _single("twofold_sumd_f32", x, None, WIDE, launch, out, ws, torch.float64)
+
+
+def dotd(x, y, launch=None, out=None, ws=None):
+    """Paper's dotd: float32 data, float64 products and accumulator."""
+    if x.dtype != torch.float32:
+        raise TypeError("dotd takes float32 data")
+    return _single("twofold_dotd_f32", x, y, WIDE, launch, out, ws, torch.float64)
+
+
+def _seg(x, y, offsets, mode, launch, out, ws):
+    L = _lib.load()
+    _check_data(*([x] if y is None else [x, y]))
+    if offsets.dtype != torch.int64 or offsets.device != x.device or offsets.dim() != 1 \
+            or not offsets.is_contiguous():
+        raise ValueError("twofold: offsets must be a contiguous int64 tensor on x's device")
+    nseg = offsets.numel() - 1
+    if nseg < 0:
+        raise ValueError("twofold: offsets must hold nseg + 1 entries")
+    dev = x.device
+    dt = x.element_size()
+    m = mode_id(mode)
+    lp = _launch_ptr(launch)
+    n_total = x.numel()
+    need = L.twofold_workspace_bytes_seg(dt, int(y is not None), m, n_total, nseg, lp)
+    if need == 0:
+        raise TwofoldError("twofold_workspace_bytes_seg", _lib.EINVAL)
+    if out is None:
+        out = torch.empty((nseg, 2), dtype=x.dtype, device=dev)
+    if ws is None:
+        ws = workspace(need, dev)
+    sfx = "f32" if x.dtype == torch.float32 else "f64"
+    if y is None:
+        check("twofold_segsum_" + sfx, getattr(L, "twofold_segsum_" + sfx)(
+            ctypes.c_void_p(x.data_ptr()), n_total, ctypes.c_void_p(offsets.data_ptr()), nseg, m, lp,
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.ptr), ws.nbytes, _stream_ptr(dev)))
+    else:
+        check("twofold_segdot_" + sfx, getattr(L, "twofold_segdot_" + sfx)(
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), n_total,
+            ctypes.c_void_p(offsets.data_ptr()), nseg, m, lp, ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(ws.ptr), ws.nbytes, _stream_ptr(dev)))
+    return out
+
+
+def segsum(x, offsets, mode="rigorous", launch=None, out=None, ws=None):
+    """Twofold sums of the CSR segments of x: (nseg, 2) tensor."""
+    return _seg(x, None, offsets, mode, launch, out, ws)
+
+
+def segdot(x, y, offsets, mode="rigorous", launch=None, out=None, ws=None):
+    """Twofold dot products of the CSR segments of x and y: (nseg, 2)."""
+    return _seg(x, y, offsets, mode, launch, out, ws)
+
+
+class SegPlan:
+    """A segmented reduction with host offsets fixed at creation; execute()
+    is one persistent kernel and may be captured into a HIP graph."""
+
+    def __init__(self, offsets_host, dtype, is_dot, mode="rigorous", launch=None):
+        import numpy as np
+        off = np.ascontiguousarray(offsets_host, dtype=np.int64)
+        self.nseg = off.size - 1
+        self.dtype = {torch.float32: 4, torch.float64: 8}.get(dtype, dtype)
+        self.is_dot = bool(is_dot)
+        self.mode = mode_id(mode)
+        self._L = _lib.load()
+        h = ctypes.c_void_p()
+        check("twofold_seg_plan_create", self._L.twofold_seg_plan_create(
+            ctypes.c_void_p(off.ctypes.data), self.nseg, self.dtype, int(self.is_dot), self.mode,
+            _launch_ptr(launch), ctypes.byref(h)))
+        self._h = h
+        self.workspace_bytes = self._L.twofold_seg_plan_workspace_bytes(h)
+        self.launch = Launch()
+        check("twofold_seg_plan_get_launch",
+              self._L.twofold_seg_plan_get_launch(h, ctypes.byref(self.launch)))
+
+    @property
+    def out_dtype(self):
+        return torch.float64 if (self.dtype == 8 or self.mode == WIDE) else torch.float32
+
+    def execute(self, x, y=None, out=None, ws=None):
+        _check_data(*([x] if y is None else [x, y]))
+        if x.element_size() != self.dtype:
+            raise TypeError("SegPlan: data type differs from the plan's")
+        if out is None:
+            out = torch.empty((self.nseg, 2), dtype=self.out_dtype, device=x.device)
+        if ws is None:
+            ws = workspace(self.workspace_bytes, x.device)
+        if self.is_dot != (y is not None):
+            raise ValueError("SegPlan: y must be given exactly for dot plans")
+        check("twofold_seg_plan_execute", self._L.twofold_seg_plan_execute(
+            self._h, ctypes.c_void_p(x.data_ptr()),
+            ctypes.c_void_p(y.data_ptr()) if y is not None else None,
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.ptr), ws.nbytes,
+            _stream_ptr(x.device)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check("twofold_seg_plan_destroy", self._L.twofold_seg_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def probe_read(x, y=None, launch=None, sink=None):
+    """Memory-only probe over the bytes of x (and y)."""
+    L = _lib.load()
+    if launch is None:
+        launch = Launch(256, 4, 2048, 0, 0)
+    elif isinstance(launch, dict):
+        launch = Launch(**launch)
+    nbytes = x.numel() * x.element_size()
+    if sink is None:
+        sink = torch.empty(launch.grid_blocks, dtype=torch.int64, device=x.device)
+    check("twofold_probe_read", L.twofold_probe_read(
+        ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()) if y is not None else None,
+        nbytes, ctypes.byref(launch), ctypes.c_void_p(sink.data_ptr()), _stream_ptr(x.device)))
+    return sink
+
+
+def probe_compute(seed, is_dot, mode, iters, launch, sink=None):
+    """Compute-only probe; seed: 64 values of the data type on the device."""
+    L = _lib.load()
+    if isinstance(launch, dict):
+        launch = Launch(**launch)
+    if sink is None:
+        sink = torch.empty(2 * launch.grid_blocks * launch.block_threads, dtype=torch.float64,
+                           device=seed.device)
+    check("twofold_probe_compute", L.twofold_probe_compute(
+        seed.element_size(), int(is_dot), mode_id(mode), ctypes.c_void_p(seed.data_ptr()), iters,
+        ctypes.byref(launch), ctypes.c_void_p(sink.data_ptr()), _stream_ptr(seed.device)))
+    return sink

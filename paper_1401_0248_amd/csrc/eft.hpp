@@ -1,0 +1,138 @@
+// eft.hpp: device-side error-free transforms and pair combines for gfx950.
+//
+// The per-element steps of the paper (Latkin, "Twofold fast summation",
+// section "Algorithms"): Example 1 (fast twofold, Dekker's Theorem 1),
+// Example 3 (rigorous twofold, Knuth's Theorem 2) and direct summation, with
+// dot products by substitution of the product for the data item; this
+// library adds the product's FMA remainder to the error. Compiled with
+// -ffp-contract=off: the single FMA below is the only fused operation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace twofold {
+
+enum Mode : int { kPlain = 0, kFast = 1, kRigorous = 2, kWide = 3 };
+
+__device__ __forceinline__ float fma_rn(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_rn(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// One data item into one chain (s, e). T is the data type, A the
+// accumulator type (A == T except in kWide, where binary32 data is widened
+// to binary64 and summed plainly).
+template <int M, bool DOT, typename T, typename A>
+__device__ __forceinline__ void step(A& s, A& e, T xv, T yv) {
+  if constexpr (M == kWide) {
+    A item = DOT ? static_cast<A>(xv) * static_cast<A>(yv) : static_cast<A>(xv);
+    s = s + item;
+  } else if constexpr (M == kPlain) {
+    T item = DOT ? xv * yv : xv;
+    s = s + item;
+  } else {
+    T p = DOT ? xv * yv : xv;
+    T t = s + p;
+    if constexpr (M == kFast) {
+      // Example 1: c = (t - s) - item is the negated round-off of s + item
+      // when |s| >= |item| (Theorem 1).
+      T c = (t - s) - p;
+      if constexpr (DOT) {
+        T pi = fma_rn(xv, yv, -p);  // x*y - p, exact
+        e = e + (pi - c);
+      } else {
+        e = e - c;
+      }
+    } else {
+      // Example 3: yt and t - yt are the parts of t attributed to the item
+      // and to s; dy + ds is the exact round-off of s + item (Theorem 2).
+      T yt = t - s;
+      T dy = p - yt;
+      T ds = s - (t - yt);
+      if constexpr (DOT) {
+        T pi = fma_rn(xv, yv, -p);
+        e = e + ((ds + dy) + pi);
+      } else {
+        e = e + (ds + dy);
+      }
+    }
+    s = t;
+  }
+}
+
+// combine((s1,e1),(s2,e2)): two-sum of the values with all six operations
+// of Theorem 2, then the errors and the two-sum remainder. Plain and wide
+// pairs carry no error.
+template <int M, typename A>
+__device__ __forceinline__ void combine(A& s1, A& e1, A s2, A e2) {
+  if constexpr (M == kPlain || M == kWide) {
+    s1 = s1 + s2;
+    e1 = A(0);
+  } else {
+    A x = s1 + s2;
+    A bp = x - s1;
+    A ap = x - bp;
+    A bh = s2 - bp;
+    A ah = s1 - ap;
+    A y = ah + bh;
+    e1 = (e1 + e2) + y;
+    s1 = x;
+  }
+}
+
+// ---- cross-lane moves: the value held by lane (lane xor D) ----------------
+// D = 1, 2: DPP quad permutations; D = 4, 8, 16: ds_swizzle in bit-mask mode
+// (lane' = lane xor mask within 32 lanes); D = 32: ds_bpermute.
+template <int D>
+__device__ __forceinline__ int xor_lane_b32(int v) {
+  if constexpr (D == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (D == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (D == 4 || D == 8 || D == 16) {
+    return __builtin_amdgcn_ds_swizzle(v, (D << 10) | 0x1F);
+  } else {
+    static_assert(D == 32, "xor distance");
+    const int lane = __lane_id();
+    return __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ float xor_lane(float v) {
+  return __int_as_float(xor_lane_b32<D>(__float_as_int(v)));
+}
+
+template <int D>
+__device__ __forceinline__ double xor_lane(double v) {
+  const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+  const int lo = xor_lane_b32<D>(static_cast<int>(static_cast<uint32_t>(u)));
+  const int hi = xor_lane_b32<D>(static_cast<int>(static_cast<uint32_t>(u >> 32)));
+  const uint64_t r = (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                     static_cast<uint64_t>(static_cast<uint32_t>(lo));
+  return __longlong_as_double(static_cast<long long>(r));
+}
+
+template <int M, int D, typename A>
+__device__ __forceinline__ void wave_stage(A& s, A& e) {
+  const A s2 = xor_lane<D>(s);
+  if constexpr (M == kPlain || M == kWide) {
+    combine<M>(s, e, s2, A(0));
+  } else {
+    const A e2 = xor_lane<D>(e);
+    combine<M>(s, e, s2, e2);
+  }
+}
+
+// Wave combine: xor distances 1, 2, 4, 8, 16, 32 in this order; every lane
+// computes combine(own, partner). All 64 lanes must be active.
+template <int M, typename A>
+__device__ __forceinline__ void wave_combine(A& s, A& e) {
+  wave_stage<M, 1>(s, e);
+  wave_stage<M, 2>(s, e);
+  wave_stage<M, 4>(s, e);
+  wave_stage<M, 8>(s, e);
+  wave_stage<M, 16>(s, e);
+  wave_stage<M, 32>(s, e);
+}
+
+}  // namespace twofold

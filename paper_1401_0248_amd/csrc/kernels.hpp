@@ -1,0 +1,346 @@
+// kernels.hpp: the twofold reduction kernels for gfx950.
+//
+// Streaming reductions bound by HBM bandwidth: 16-byte vector loads
+// (global_load_dwordx4), U independent loads in flight per lane, W = 16 /
+// sizeof(T) independent (s, e) chains per lane, then pair combines across
+// chains, lanes (DPP / ds_swizzle / ds_bpermute), waves (LDS) and blocks
+// (binary64, in one fixed order). No matrix cores: there is no contraction
+// to feed them. The order is the one documented in include/twofold.h; it
+// depends only on the launch configuration and the inputs, so results are
+// identical run to run.
+#pragma once
+
+#include "eft.hpp"
+
+namespace twofold {
+
+constexpr uint32_t kMagic = 0x54574F46u;  // "TWOF": workspace prepared
+constexpr int kHdrMagic = 0;              // header words (uint32)
+constexpr int kHdrCounter = 1;            // blocks done (single vector)
+constexpr int kHdrStatus = 2;             // 0 ok, 1 invalid segment offsets
+constexpr int kPass2Lanes = 256;          // lanes of the binary64 grid combine
+
+template <typename T> struct vec16;
+template <> struct vec16<float> { using type = float4; };
+template <> struct vec16<double> { using type = double2; };
+
+template <typename T>
+__device__ __forceinline__ T vget(const typename vec16<T>::type& v, int j);
+template <>
+__device__ __forceinline__ float vget<float>(const float4& v, int j) {
+  return j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.z : v.w;
+}
+template <>
+__device__ __forceinline__ double vget<double>(const double2& v, int j) {
+  return j == 0 ? v.x : v.y;
+}
+
+// Load W consecutive elements starting at p + k*W. With ALIGNED the
+// address is 16-byte aligned and one vector load is used; otherwise the
+// elements are loaded one by one (same values, same order of use).
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ typename vec16<T>::type load_vec(const T* __restrict__ p, int64_t k) {
+  using V = typename vec16<T>::type;
+  if constexpr (ALIGNED) {
+    return reinterpret_cast<const V*>(p)[k];
+  } else {
+    V v;
+    const T* q = p + k * (16 / static_cast<int64_t>(sizeof(T)));
+    if constexpr (sizeof(T) == 4) {
+      v.x = q[0];
+      v.y = q[1];
+      v.z = q[2];
+      v.w = q[3];
+    } else {
+      v.x = q[0];
+      v.y = q[1];
+    }
+    return v;
+  }
+}
+
+// Elements before the first 16-byte boundary at or after p, capped at len.
+template <typename T>
+__device__ __forceinline__ int64_t head_count(const T* p, int64_t len) {
+  const int64_t mis = static_cast<int64_t>(reinterpret_cast<uintptr_t>(p) & 15u) /
+                      static_cast<int64_t>(sizeof(T));
+  const int64_t W = 16 / static_cast<int64_t>(sizeof(T));
+  const int64_t h = (W - mis) % W;
+  return h < len ? h : len;
+}
+
+// Steps 1-4 of the documented order for one lane g of L lanes over the
+// range [x, x + len): head, rounds of U vectors, tail, chain merge.
+template <typename T, typename A, int M, bool DOT, bool YV, int U>
+__device__ __forceinline__ void lane_reduce(const T* __restrict__ x, const T* __restrict__ y,
+                                            int64_t len, int64_t head, int64_t L, int64_t g,
+                                            A& s_out, A& e_out) {
+  constexpr int W = 16 / static_cast<int>(sizeof(T));
+  using V = typename vec16<T>::type;
+  A cs[W], ce[W];
+#pragma unroll
+  for (int j = 0; j < W; j++) {
+    cs[j] = A(0);
+    ce[j] = A(0);
+  }
+  if (g < head) step<M, DOT>(cs[0], ce[0], x[g], DOT ? y[g] : T(0));
+  const T* __restrict__ xb = x + head;
+  const T* __restrict__ yb = DOT ? y + head : nullptr;
+  const int64_t nv = (len - head) / W;
+  const int64_t per_round = static_cast<int64_t>(U) * L;
+  const int64_t full = nv / per_round;
+  int64_t k0 = g;
+  for (int64_t q = 0; q < full; q++, k0 += per_round) {
+    V a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) a[u] = load_vec<T, true>(xb, k0 + u * L);
+    if constexpr (DOT) {
+#pragma unroll
+      for (int u = 0; u < U; u++) b[u] = load_vec<T, YV>(yb, k0 + u * L);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+#pragma unroll
+      for (int j = 0; j < W; j++)
+        step<M, DOT>(cs[j], ce[j], vget<T>(a[u], j), DOT ? vget<T>(b[u], j) : T(0));
+    }
+  }
+  // Last, partial round: vectors k0 + u*L below nv, u in order.
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int64_t k = k0 + u * L;
+    if (k < nv) {
+      V a = load_vec<T, true>(xb, k);
+      V b = a;
+      if constexpr (DOT) b = load_vec<T, YV>(yb, k);
+#pragma unroll
+      for (int j = 0; j < W; j++)
+        step<M, DOT>(cs[j], ce[j], vget<T>(a, j), DOT ? vget<T>(b, j) : T(0));
+    }
+  }
+  const int64_t tail0 = nv * W;
+  if (g < (len - head) - tail0) {
+    step<M, DOT>(cs[0], ce[0], xb[tail0 + g], DOT ? yb[tail0 + g] : T(0));
+  }
+  A s = cs[0], e = ce[0];
+#pragma unroll
+  for (int j = 1; j < W; j++) combine<M>(s, e, cs[j], ce[j]);
+  s_out = s;
+  e_out = e;
+}
+
+// Step 8: binary64 (V, E) into the output pair.
+template <typename T, int M>
+__device__ __forceinline__ void finalize_store(void* __restrict__ out, int64_t idx, double V,
+                                               double E) {
+  if constexpr (sizeof(T) == 8 || M == kWide) {
+    reinterpret_cast<double2*>(out)[idx] = make_double2(V, E);
+  } else {
+    const float v = static_cast<float>(V);
+    float e = 0.0f;
+    if constexpr (M != kPlain) e = static_cast<float>((V - static_cast<double>(v)) + E);
+    reinterpret_cast<float2*>(out)[idx] = make_float2(v, e);
+  }
+}
+
+__device__ __forceinline__ void store_nan_pair(void* out, int64_t idx, bool f64_pair) {
+  if (f64_pair)
+    reinterpret_cast<double2*>(out)[idx] = make_double2(__builtin_nan(""), __builtin_nan(""));
+  else
+    reinterpret_cast<float2*>(out)[idx] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+}
+
+template <typename T, int M>
+constexpr bool out_is_f64() {
+  return sizeof(T) == 8 || M == kWide;
+}
+
+// ---- single vector ----------------------------------------------------------
+// One pair per block into part[] (binary64); the last block to finish, found
+// with an agent-scope counter in the workspace header, combines all block
+// pairs in index order (step 7) and resets the counter for the next call.
+template <typename T, typename A, int M, bool DOT, bool YV, int U>
+__global__ void __launch_bounds__(1024)
+single_kernel(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
+              uint32_t* __restrict__ hdr, double* __restrict__ part, void* __restrict__ out) {
+  __shared__ A sh_s[16], sh_e[16];
+  __shared__ double sh_qs[4], sh_qe[4];
+  __shared__ int sh_last;
+  const int nblocks = static_cast<int>(gridDim.x);
+  if (nblocks > 1 && hdr[kHdrMagic] != kMagic) {
+    // Workspace never prepared: refuse loudly rather than race on garbage.
+    if (blockIdx.x == 0 && threadIdx.x == 0) store_nan_pair(out, 0, out_is_f64<T, M>());
+    return;
+  }
+  const int64_t L = static_cast<int64_t>(nblocks) * blockDim.x;
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t head = head_count(x, n);
+  A s, e;
+  lane_reduce<T, A, M, DOT, YV, U>(x, y, n, head, L, g, s, e);
+  wave_combine<M>(s, e);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  if (lane == 0) {
+    sh_s[wave] = s;
+    sh_e[wave] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    A bs = sh_s[0], be = sh_e[0];
+    for (int w = 1; w < nw; w++) combine<M>(bs, be, sh_s[w], sh_e[w]);
+    if (nblocks == 1) {
+      finalize_store<T, M>(out, 0, static_cast<double>(bs), static_cast<double>(be));
+    } else {
+      part[2 * blockIdx.x] = static_cast<double>(bs);
+      part[2 * blockIdx.x + 1] = static_cast<double>(be);
+      const uint32_t done = __hip_atomic_fetch_add(&hdr[kHdrCounter], 1u, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+      sh_last = (done == static_cast<uint32_t>(nblocks - 1)) ? 1 : 0;
+    }
+  }
+  if (nblocks == 1) return;
+  __syncthreads();
+  if (!sh_last) return;
+  // Every block's pair is visible: acquire at agent scope for all waves.
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (threadIdx.x < kPass2Lanes) {
+    double qs = 0.0, qe = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += kPass2Lanes)
+      combine<M>(qs, qe, part[2 * i], part[2 * i + 1]);
+    wave_combine<M>(qs, qe);
+    if (lane == 0) {
+      sh_qs[wave] = qs;
+      sh_qe[wave] = qe;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double V = sh_qs[0], E = sh_qe[0];
+    for (int w = 1; w < kPass2Lanes / 64; w++) combine<M>(V, E, sh_qs[w], sh_qe[w]);
+    finalize_store<T, M>(out, 0, V, E);
+    __hip_atomic_store(&hdr[kHdrCounter], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---- segmented ---------------------------------------------------------------
+// Persistent waves over a tile list. tbase[s] = number of tiles of segments
+// before s (tbase[nseg] = total). Wave w takes tiles
+// [floor(w*NT/NW), floor((w+1)*NT/NW)). A one-tile segment is finalized by
+// its wave; otherwise each tile pair goes to slots[tile] and the wave that
+// completes a segment (per-segment counter) combines its tiles in order.
+template <typename T, typename A, int M, bool DOT, bool YV, int U>
+__global__ void __launch_bounds__(1024)
+seg_kernel(const T* __restrict__ x, const T* __restrict__ y, const int64_t* __restrict__ off,
+           int64_t nseg, const int64_t* __restrict__ tbase, int64_t TS, int check_status,
+           uint32_t* __restrict__ hdr, uint32_t* __restrict__ cnt, double* __restrict__ slots,
+           void* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6);
+  const int64_t NW = static_cast<int64_t>(gridDim.x) * wpb;
+  const int64_t gtid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nthreads = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const bool bad = hdr[kHdrMagic] != kMagic || (check_status && hdr[kHdrStatus] != 0);
+  for (int64_t sg = gtid; sg < nseg; sg += nthreads) {
+    if (bad)
+      store_nan_pair(out, sg, out_is_f64<T, M>());
+    else if (off[sg + 1] == off[sg])
+      finalize_store<T, M>(out, sg, 0.0, 0.0);
+  }
+  if (bad) return;
+  const int64_t NT = tbase[nseg];
+  const int64_t t0 = (w * NT) / NW, t1 = ((w + 1) * NT) / NW;
+  if (t0 >= t1) return;
+  // Segment of tile t0: tbase[lo] <= t0 < tbase[lo + 1].
+  int64_t lo = 0, hi = nseg;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (tbase[mid] <= t0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  int64_t sg = lo;
+  for (int64_t t = t0; t < t1; t++) {
+    while (tbase[sg + 1] <= t) sg++;
+    const int64_t tb = tbase[sg];
+    const int64_t ntl = tbase[sg + 1] - tb;
+    const int64_t a = off[sg] + (t - tb) * TS;
+    const int64_t b = (off[sg + 1] < a + TS) ? off[sg + 1] : a + TS;
+    const T* xa = x + a;
+    const T* ya = DOT ? y + a : nullptr;
+    A s, e;
+    lane_reduce<T, A, M, DOT, YV, U>(xa, ya, b - a, head_count(xa, b - a), 64, lane, s, e);
+    wave_combine<M>(s, e);
+    if (ntl == 1) {
+      if (lane == 0) finalize_store<T, M>(out, sg, static_cast<double>(s), static_cast<double>(e));
+      continue;
+    }
+    uint32_t done = 0;
+    if (lane == 0) {
+      slots[2 * t] = static_cast<double>(s);
+      slots[2 * t + 1] = static_cast<double>(e);
+      done = __hip_atomic_fetch_add(&cnt[sg], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    done = __shfl(done, 0);
+    if (done != static_cast<uint32_t>(ntl - 1)) continue;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double qs = 0.0, qe = 0.0;
+    for (int64_t i = lane; i < ntl; i += 64) combine<M>(qs, qe, slots[2 * (tb + i)], slots[2 * (tb + i) + 1]);
+    wave_combine<M>(qs, qe);
+    if (lane == 0) {
+      finalize_store<T, M>(out, sg, qs, qe);
+      __hip_atomic_store(&cnt[sg], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Tile table from device offsets (one block of 1024 threads), rows of 1024
+// segments: tiles per segment, block-wide exclusive scan, running carry.
+// Also clears the per-segment counters and records whether the offsets are
+// valid (offsets[0] >= 0, non-decreasing, offsets[nseg] <= n_total).
+__global__ void __launch_bounds__(1024)
+seg_tiles_kernel(const int64_t* __restrict__ off, int64_t nseg, int64_t n_total, int64_t TS,
+                 int64_t* __restrict__ tbase, uint32_t* __restrict__ hdr,
+                 uint32_t* __restrict__ cnt) {
+  __shared__ int64_t sh[1024];
+  __shared__ int sh_bad;
+  const int t = threadIdx.x;
+  if (t == 0) sh_bad = (off[0] < 0 || off[nseg] > n_total) ? 1 : 0;
+  __syncthreads();
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nseg; base += 1024) {
+    const int64_t sg = base + t;
+    int64_t tiles = 0;
+    if (sg < nseg) {
+      const int64_t len = off[sg + 1] - off[sg];
+      if (len < 0) sh_bad = 1;  // benign race: every writer stores 1
+      tiles = len > 0 ? (len + TS - 1) / TS : 0;
+      cnt[sg] = 0u;
+    }
+    sh[t] = tiles;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+      const int64_t v = t >= d ? sh[t - d] : 0;
+      __syncthreads();
+      sh[t] += v;
+      __syncthreads();
+    }
+    if (sg < nseg) tbase[sg] = carry + sh[t] - tiles;
+    carry += sh[1023];
+    __syncthreads();
+  }
+  if (t == 0) {
+    tbase[nseg] = carry;
+    hdr[kHdrStatus] = sh_bad ? 1u : 0u;
+  }
+}
+
+// Workspace preparation: zero everything, then stamp the header.
+__global__ void ws_init_kernel(uint32_t* __restrict__ ws, int64_t nwords) {
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = i0; i < nwords; i += stride) ws[i] = (i == kHdrMagic) ? kMagic : 0u;
+}
+
+}  // namespace twofold

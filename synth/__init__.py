@@ -150,7 +150,7 @@ def illcond_dot(seed, n, cond, dtype, calibrate=True):
     order 1 while sum |x y| grows with n), so with ``calibrate`` the same
     draws are used once more with h lowered by
     round(log2(estimate / cond) / 2), the estimate being
-    2 * sum|x y| (binary64) / |final running dot| (binary128, rounded).
+    2 * sum|x y| (binary64) / |final running dot| (x87 extended, rounded).
     The exact achieved condition must still be measured by the caller."""
     if n < 4 or n % 2:
         raise ValueError("illcond_dot: n must be even and >= 4")

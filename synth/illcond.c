@@ -3,10 +3,12 @@
  *
  * Input generator only: it makes data, it computes no result of the
  * summation methods. The running dot P of the elements generated so far is
- * kept in binary128 (__float128): products of two binary64 (or binary32)
- * numbers are exact there, and the sum rounds at 2^-113 relative. Each new
- * y_i is chosen so that x_i*y_i cancels P toward m'_i * 2^(e_i):
- *     y_i = fl_T((m'_i * 2^e_i - P) / x_i)      (quotient in binary128)
+ * kept in x87 extended precision (long double, 64-bit significand): the
+ * products of two binary32 numbers are exact there, those of two binary64
+ * numbers round at 2^-64 relative, which is ample for steering the
+ * cancellation. Each new y_i is chosen so that x_i*y_i cancels P toward
+ * m'_i * 2^(e_i):
+ *     y_i = fl_T((m'_i * 2^e_i - P) / x_i)      (quotient in extended)
  * and e_i decays linearly from hi_exp to 0 over the second half.
  */
 #include <math.h>
@@ -28,8 +30,8 @@ static int decay_exp(int64_t i, int64_t n0, int64_t n, int hi_exp) {
  * rounded to binary64, an estimate used only to calibrate the recipe. */
 int64_t synth_illcond_tail_f64(double* x, double* y, int64_t n0, int64_t n, const double* mx,
                                const double* my, int hi_exp, double tiny, double* p_final) {
-  __float128 P = 0;
-  for (int64_t i = 0; i < n0; i++) P += (__float128)x[i] * (__float128)y[i];
+  long double P = 0;
+  for (int64_t i = 0; i < n0; i++) P += (long double)x[i] * (long double)y[i];
   int64_t small = 0;
   for (int64_t i = n0; i < n; i++) {
     int e = decay_exp(i, n0, n, hi_exp);
@@ -39,10 +41,10 @@ int64_t synth_illcond_tail_f64(double* x, double* y, int64_t n0, int64_t n, cons
     if (xi == 0)
       yi = target;
     else
-      yi = (double)(((__float128)target - P) / (__float128)xi);
+      yi = (double)(((long double)target - P) / (long double)xi);
     x[i] = xi;
     y[i] = yi;
-    __float128 p = (__float128)xi * (__float128)yi;
+    long double p = (long double)xi * (long double)yi;
     if (p != 0 && fabs((double)p) < tiny) small++;
     P += p;
   }
@@ -52,8 +54,8 @@ int64_t synth_illcond_tail_f64(double* x, double* y, int64_t n0, int64_t n, cons
 
 int64_t synth_illcond_tail_f32(float* x, float* y, int64_t n0, int64_t n, const double* mx,
                                const double* my, int hi_exp, double tiny, double* p_final) {
-  __float128 P = 0;
-  for (int64_t i = 0; i < n0; i++) P += (__float128)x[i] * (__float128)y[i];
+  long double P = 0;
+  for (int64_t i = 0; i < n0; i++) P += (long double)x[i] * (long double)y[i];
   int64_t small = 0;
   for (int64_t i = n0; i < n; i++) {
     int e = decay_exp(i, n0, n, hi_exp);
@@ -63,10 +65,10 @@ int64_t synth_illcond_tail_f32(float* x, float* y, int64_t n0, int64_t n, const 
     if (xi == 0)
       yi = target;
     else
-      yi = (float)(((__float128)target - P) / (__float128)xi);
+      yi = (float)(((long double)target - P) / (long double)xi);
     x[i] = xi;
     y[i] = yi;
-    __float128 p = (__float128)xi * (__float128)yi;
+    long double p = (long double)xi * (long double)yi;
     if (p != 0 && fabs((double)p) < tiny) small++;
     P += p;
   }

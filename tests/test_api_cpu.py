@@ -1,0 +1,165 @@
+"""The C interface without a GPU: the library loads, exports every function
+include/twofold.h declares, and rejects bad arguments on the host before
+any HIP call (so these calls are safe on a machine with no GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1401_0248_amd import _lib
+from paper_1401_0248_amd._lib import EALIGN, EINVAL, EOFFSETS, EWORKSPACE, Launch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "twofold.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(twofold_\w+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib.load()
+    names = _declared()
+    assert len(names) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.lib_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (twofold_\w+)", out))
+    for n in names:
+        assert n in exported, n
+        assert hasattr(L, n)
+    # and the binding declares a signature for each of them
+    assert set(names) == set(_lib.SIGNATURES)
+
+
+def test_product_does_not_touch_the_oracle():
+    out = subprocess.run(["nm", "-D", _lib.lib_path()], capture_output=True, text=True).stdout
+    assert "oracle" not in out
+    pkg = os.path.join(ROOT, "paper_1401_0248_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".inc", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "twofold_oracle" not in src, f
+
+
+def test_header_compiles_as_c():
+    src = '#include "twofold.h"\nint main(void){ twofold_launch_t l = {0}; (void)l; return 0; }\n'
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        "-x", "c", "-", "-fsyntax-only"], input=src, text=True, capture_output=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_strerror():
+    L = _lib.load()
+    for code in (0, -1, -2, -3, -4, -5, 7):
+        assert isinstance(L.twofold_strerror(code), bytes)
+
+
+def test_single_argument_checks():
+    L = _lib.load()
+    fake = ctypes.c_void_p(0x10000)  # never dereferenced: checks fail first
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 20
+    # null pointers, negative n, bad modes
+    assert L.twofold_sum_f32(None, 10, 2, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_sum_f32(fake, -1, 2, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_sum_f32(fake, 10, 7, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_sum_f32(fake, 10, 3, None, fake, ws, big, None) == EINVAL  # wide: use sumd
+    assert L.twofold_sum_f64(fake, 10, 3, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_dot_f64(fake, None, 10, 2, None, fake, ws, big, None) == EINVAL
+    # misaligned data
+    assert L.twofold_sum_f64(ctypes.c_void_p(0x10004), 10, 2, None, fake, ws, big, None) == EALIGN
+    assert L.twofold_dot_f32(fake, ctypes.c_void_p(0x10002), 10, 2, None, fake, ws, big, None) == EALIGN
+    # workspace missing, misaligned, too small
+    assert L.twofold_sum_f32(fake, 10, 2, None, fake, None, big, None) == EWORKSPACE
+    assert L.twofold_sum_f32(fake, 10, 2, None, fake, ctypes.c_void_p(0x100010), big, None) == EWORKSPACE
+    assert L.twofold_sum_f32(fake, 1 << 24, 2, None, fake, ws, 512, None) == EWORKSPACE
+    # bad launches
+    for lc in (Launch(100, 4, 1, 0, 0), Launch(256, 3, 1, 0, 0), Launch(256, 4, -1, 0, 0),
+               Launch(256, 4, 1, 1, 0), Launch(64, 4, 1, 0, 0), Launch(256, 4, (1 << 20) + 1, 0, 0)):
+        assert L.twofold_sum_f32(fake, 10, 2, ctypes.byref(lc), fake, ws, big, None) == EINVAL
+
+
+def test_workspace_sizes():
+    L = _lib.load()
+    for dt in (4, 8):
+        for dot in (0, 1):
+            b = L.twofold_workspace_bytes_single(dt, dot, 2, 1 << 24, None)
+            lc = Launch()
+            assert L.twofold_default_launch(0, dt, dot, 2, 1 << 24, 0, ctypes.byref(lc)) == 0
+            assert b == 256 + ((16 * lc.grid_blocks + 255) // 256) * 256
+            assert L.twofold_workspace_bytes_single(dt, dot, 2, 0, None) >= 256
+    lc = Launch(256, 4, 7, 0, 0)
+    assert L.twofold_workspace_bytes_single(8, 1, 2, 100, ctypes.byref(lc)) == 256 + 256
+    # explicit grid is used as given
+    assert L.twofold_default_launch(0, 8, 1, 2, 0, 0, ctypes.byref(lc)) == 0 and lc.grid_blocks == 1
+    assert L.twofold_workspace_bytes_single(16, 1, 2, 100, None) == 0
+    s = L.twofold_workspace_bytes_seg(4, 1, 2, 1 << 20, 1000, None)
+    assert s > 256 + 4 * 1000 + 8 * 1001
+
+
+def test_default_launch_grid_scales_with_n():
+    L = _lib.load()
+    lc = Launch()
+    grids = []
+    for n in (0, 1000, 1 << 16, 1 << 20, 1 << 28):
+        assert L.twofold_default_launch(0, 4, 0, 2, n, 0, ctypes.byref(lc)) == 0
+        grids.append(lc.grid_blocks)
+        assert lc.block_threads in (256, 512, 1024) and lc.unroll in (1, 2, 4, 8)
+    assert grids[0] == 1 and grids == sorted(grids) and grids[-1] > 1
+
+
+def test_segmented_argument_checks():
+    L = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    ws = ctypes.c_void_p(0x100000)
+    assert L.twofold_segsum_f32(fake, 10, None, 3, 2, None, fake, ws, 1 << 20, None) == EINVAL
+    assert L.twofold_segsum_f32(fake, 10, fake, -1, 2, None, fake, ws, 1 << 20, None) == EINVAL
+    assert L.twofold_segsum_f32(fake, 10, fake, 3, 3, None, fake, ws, 1 << 20, None) == EINVAL
+    assert L.twofold_segsum_f64(fake, 10, ctypes.c_void_p(0x10004), 3, 2, None, fake, ws, 1 << 20,
+                                None) == EALIGN
+    assert L.twofold_segdot_f64(fake, fake, 1 << 20, fake, 5000, 2, None, fake, ws, 1024, None) == EWORKSPACE
+    lc = Launch(256, 4, 16, 0, 1000)  # tile not a multiple of 64*W
+    assert L.twofold_segsum_f32(fake, 10, fake, 3, 2, ctypes.byref(lc), fake, ws, 1 << 20, None) == EINVAL
+    # nseg == 0: nothing to do, nothing launched
+    assert L.twofold_segsum_f32(fake, 0, fake, 0, 2, None, fake, ws, 1 << 20, None) == 0
+
+
+def test_plan_rejects_bad_offsets_before_any_hip_call():
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    for off in ([1, 5, 9], [0, 5, 3], [0, -1]):
+        a = np.array(off, dtype=np.int64)
+        assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), a.size - 1, 4, 0, 2, None,
+                                         ctypes.byref(h)) == EOFFSETS
+        assert not h.value
+    a = np.array([0, 5], dtype=np.int64)
+    assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 8, 0, 3, None,
+                                     ctypes.byref(h)) == EINVAL  # wide needs binary32
+    assert L.twofold_seg_plan_create(None, 1, 4, 0, 2, None, ctypes.byref(h)) == EINVAL
+    assert L.twofold_seg_plan_destroy(None) == 0
+    assert L.twofold_seg_plan_workspace_bytes(None) == 0
+
+
+def test_probe_argument_checks():
+    L = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    lc = Launch(256, 4, 8, 0, 0)
+    assert L.twofold_probe_read(fake, None, 100, ctypes.byref(lc), fake, None) == EINVAL
+    assert L.twofold_probe_read(ctypes.c_void_p(0x10008), None, 160, ctypes.byref(lc), fake,
+                                None) == EALIGN
+    assert L.twofold_probe_read(fake, None, 160, None, fake, None) == EINVAL
+    assert L.twofold_probe_compute(8, 0, 3, fake, 10, ctypes.byref(lc), fake, None) == EINVAL
+
+
+@pytest.mark.parametrize("bad", [0, 16, 128])
+def test_workspace_init_checks(bad):
+    L = _lib.load()
+    assert L.twofold_workspace_init(None, 1024, None) == EWORKSPACE
+    assert L.twofold_workspace_init(ctypes.c_void_p(0x100000), bad, None) == EWORKSPACE

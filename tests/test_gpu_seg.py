@@ -1,0 +1,161 @@
+"""GPU parity of the segmented (CSR) reductions: device-offset entry points
+and plans, bitwise against the order model and within the rigorous bound."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1401_0248_amd as tf
+import synth
+from gpu_helpers import DEV, launch, same_bits, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _u(dtype):
+    return 2.0 ** -(np.finfo(dtype).nmant + 1)
+
+
+def _lengths():
+    # empty, one element, exactly one tile, one past, many tiles, ragged
+    return np.array([0, 1, 3, 256, 257, 1024, 1025, 5000, 0, 0, 77, 12345, 2, 65536 + 7, 0, 9],
+                    dtype=np.int64)
+
+
+def _rows(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("is_dot", [False, True])
+@pytest.mark.parametrize("mode", ["plain", "fast", "rigorous"])
+def test_seg_bitwise_vs_model(dtype, is_dot, mode):
+    W = 16 // np.dtype(dtype).itemsize
+    L = _lengths()
+    off = synth.offsets_from_lengths(L)
+    n = int(off[-1])
+    rng = np.random.default_rng(3)
+    x = (rng.standard_normal(n) * np.exp2(rng.integers(-8, 8, n))).astype(dtype)
+    y = rng.standard_normal(n).astype(dtype)
+    for ts, u, gb, bt, xs, ys in ((64 * W, 1, 1, 64, 0, 0), (64 * W * 4, 4, 3, 256, 1, 0),
+                                  (64 * W * 16, 8, 50, 512, 3, 3), (64 * W * 2, 2, 1000, 128, 2, 1)):
+        xd, mis = to_dev(x, xs)
+        yd, _ = to_dev(y, ys) if is_dot else (None, 0)
+        od = torch.from_numpy(off).to(DEV)
+        lc = launch(bt, u, gb, ts)
+        got = tf.segdot(xd, yd, od, mode, lc) if is_dot else tf.segsum(xd, od, mode, lc)
+        want = oracle.model_seg(mode, x, off, y if is_dot else None, mis, u, ts)
+        g = _rows(got)
+        for s in range(len(L)):
+            assert same_bits(g[s], want[s]), (s, L[s], ts, u, gb, list(g[s]), list(want[s]))
+        # the plan path gives the same bits
+        plan = tf.SegPlan(off, xd.dtype, is_dot, mode, lc)
+        got2 = plan.execute(xd, yd if is_dot else None)
+        assert torch.equal(got2, got)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_seg_bound_default_launch(dtype):
+    u = _u(dtype)
+    L = synth.segment_lengths(3, 500, max_len=1 << 16)
+    off = synth.offsets_from_lengths(L)
+    x, y = synth.uniform(33, int(off[-1]), dtype, count=2)
+    xd, _ = to_dev(x)
+    yd, _ = to_dev(y)
+    od = torch.from_numpy(off).to(DEV)
+    gd = _rows(tf.segdot(xd, yd, od, "rigorous"))
+    gs = _rows(tf.segsum(xd, od, "rigorous"))
+    gf = _rows(tf.segsum(xd, od, "fast"))
+    for s in range(0, len(L), 7):
+        a, b = off[s], off[s + 1]
+        ex = oracle.Exact(x[a:b], y[a:b])
+        assert abs(ex.diff(*gd[s])) <= 4 * (b - a) * u * u * ex.A
+        exs = oracle.Exact(x[a:b])
+        assert exs.diff(*gs[s]) == 0.0 and exs.diff(*gf[s]) == 0.0
+
+
+def test_wide_plan_vs_model():
+    L = _lengths()
+    off = synth.offsets_from_lengths(L)
+    x, y = synth.uniform(4, int(off[-1]), np.float32, count=2)
+    xd, mis = to_dev(x, 1)
+    yd, _ = to_dev(y, 0)
+    lc = launch(256, 4, 17, 1024)
+    for is_dot in (False, True):
+        plan = tf.SegPlan(off, torch.float32, is_dot, "wide", lc)
+        got = _rows(plan.execute(xd, yd if is_dot else None))
+        want = oracle.model_seg("wide", x, off, y if is_dot else None, mis, 4, 1024)
+        for s in range(len(L)):
+            assert same_bits(got[s], want[s]), s
+
+
+def test_invalid_device_offsets_give_nan():
+    x = torch.ones(100, dtype=torch.float32, device=DEV)
+    for bad in ([0, 50, 40, 100], [0, 50, 101], [-1, 5, 10]):
+        od = torch.tensor(bad, dtype=torch.int64, device=DEV)
+        out = _rows(tf.segsum(x, od, "rigorous"))
+        assert np.all(np.isnan(out)), bad
+    # a valid call on the same workspace afterwards is fine again
+    od = torch.tensor([0, 50, 50, 100], dtype=torch.int64, device=DEV)
+    out = _rows(tf.segsum(x, od, "rigorous"))
+    assert list(out[:, 0]) == [50.0, 0.0, 50.0] and list(out[:, 1]) == [0.0, 0.0, 0.0]
+
+
+def test_plan_graph_replay():
+    L = synth.segment_lengths(7, 300, max_len=1 << 15)
+    off = synth.offsets_from_lengths(L)
+    x, y = synth.uniform(8, int(off[-1]), np.float64, count=2)
+    xd, _ = to_dev(x)
+    yd, _ = to_dev(y)
+    plan = tf.SegPlan(off, torch.float64, True, "rigorous")
+    eager = plan.execute(xd, yd).clone()
+    out = torch.empty_like(eager)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ws = tf.workspace(plan.workspace_bytes, xd.device)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.execute(xd, yd, out=out, ws=ws)
+    for i in range(5):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), i
+        plan.execute(yd, xd)
+        torch.cuda.synchronize()
+    for _ in range(20):
+        assert torch.equal(plan.execute(xd, yd), eager)
+
+
+def test_plan_after_device_path_on_shared_workspace():
+    """A device-offset call with few segments, then one with many, then a
+    plan with many more, all on the same per-stream workspace: the plan's
+    counters are its own, so earlier calls cannot disturb it."""
+    W = 4
+    for nseg_dev, nseg_plan in ((10, 3000), (3000, 10), (500, 500)):
+        L = synth.segment_lengths(nseg_dev + nseg_plan, nseg_plan, max_len=1 << 13)
+        off = synth.offsets_from_lengths(L)
+        x = synth.uniform(1, int(off[-1]), np.float32)
+        xd, mis = to_dev(x)
+        Ld = synth.segment_lengths(nseg_dev, nseg_dev, max_len=1 << 13)
+        offd = synth.offsets_from_lengths(Ld)
+        xdev, _ = to_dev(synth.uniform(2, int(offd[-1]), np.float32))
+        tf.segsum(xdev, torch.from_numpy(offd).to(DEV), "rigorous", launch(256, 4, 64, 64 * W))
+        plan = tf.SegPlan(off, torch.float32, False, "rigorous", launch(256, 4, 64, 64 * W))
+        got = _rows(plan.execute(xd))
+        want = oracle.model_seg("rigorous", x, off, None, mis, 4, 64 * W)
+        assert all(same_bits(got[s], want[s]) for s in range(len(L)))
+
+
+def test_many_tiny_segments():
+    L = np.ones(100000, dtype=np.int64)
+    L[::3] = 0
+    off = synth.offsets_from_lengths(L)
+    x = synth.uniform(2, int(off[-1]), np.float32)
+    xd, _ = to_dev(x)
+    od = torch.from_numpy(off).to(DEV)
+    got = _rows(tf.segsum(xd, od, "rigorous"))
+    want = np.zeros(L.size)
+    want[L == 1] = x
+    assert np.array_equal(got[:, 0], want) and np.all(got[:, 1] == 0)
