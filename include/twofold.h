@@ -75,10 +75,16 @@
  * (NULL: the legacy default stream). Calls are asynchronous: results are in
  * out once the stream reaches them. The execute paths never allocate, free
  * or synchronise, and may be captured into a HIP graph.
- * Workspace: ws must hold at least the bytes the matching
- * twofold_workspace_bytes_* call returns and must have been prepared once
- * by twofold_workspace_init; every call leaves it prepared. One workspace
- * must not be used by two calls that may run at the same time.
+ * Workspace: ws is device scratch of at least the bytes the matching
+ * twofold_workspace_bytes_* call returns, 256-byte aligned; it needs no
+ * preparation and holds nothing useful afterwards. Calls that may run at
+ * the same time need separate workspaces. A single-vector call that runs
+ * one block does not touch ws (it may then be NULL).
+ * Kernels: a single-vector call is one kernel (one block) or two (blocks,
+ * then the binary64 combine); a segmented call is the tiling kernel (device
+ * offsets only), the tile kernel and the per-segment combine kernel. Later
+ * kernels see earlier ones' results through the stream order alone: no
+ * kernel waits on, or fences for, another block.
  * Status: 0 on success, a negative TWOFOLD_E* code otherwise; arguments are
  * checked on the host before any HIP call, and nothing is launched on
  * error. Non-finite inputs give IEEE values and an unspecified error.
@@ -114,8 +120,7 @@ enum {
 };
 
 /* Launch configuration. Zero fields take the tuned default.
- *   block_threads: threads per block, 256, 512 or 1024 (single vector);
- *                  64..1024 in steps of 64 (segmented).
+ *   block_threads: threads per block, 64..1024 in steps of 64.
  *   unroll:        vectors per lane per round: 1, 2, 4 or 8.
  *   grid_blocks:   single vector: exactly this many blocks, 1..1048576;
  *                  segmented: persistent blocks, 1..1048576.
@@ -141,8 +146,6 @@ size_t twofold_workspace_bytes_single(int dtype, int is_dot, int mode, int64_t n
                                       const twofold_launch_t* launch);
 size_t twofold_workspace_bytes_seg(int dtype, int is_dot, int mode, int64_t n_total, int64_t nseg,
                                    const twofold_launch_t* launch);
-/* Prepare a workspace (zero it and stamp its header) on stream. */
-int twofold_workspace_init(void* ws, size_t ws_bytes, void* stream);
 
 /* ---- single vector: one (value, error) pair into *out (device) ---------
  * Section "Algorithms": sumtf (Example 1), sumt and sum (Example 3), dot by
@@ -168,7 +171,7 @@ int twofold_dotd_f32(const float* x, const float* y, int64_t n, const twofold_la
 /* ---- segmented (CSR) batches: nseg pairs into out[0..nseg) ---------------
  * offsets: device int64[nseg + 1], non-decreasing, offsets[0] >= 0 and
  * offsets[nseg] <= n_total (the length of x and y). Checked on the device:
- * on violation every out[s] is NaN. Two kernels (tiling, then reduction).
+ * on violation every out[s] is NaN.
  * mode TWOFOLD_WIDE is not accepted here (see the plan interface). */
 int twofold_segsum_f32(const float* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
                        int mode, const twofold_launch_t* launch, twofold_f32_t* out, void* ws,
@@ -187,10 +190,11 @@ int twofold_segdot_f64(const double* x, const double* y, int64_t n_total, const 
  * create: validates offsets_host (host int64[nseg+1], offsets[0] = 0,
  * non-decreasing), builds the tile table and copies offsets and table to
  * device memory owned by the plan, with the plan's per-segment completion
- * counters (synchronous; not capturable). The workspace of an execute
- * holds only the tile pairs.
+ * (synchronous; not capturable). The workspace of an execute holds the
+ * pairs of the tiles of multi-tile segments.
  * dtype 4 or 8; mode TWOFOLD_* (WIDE only with dtype 4).
- * execute: one persistent kernel on stream; out is twofold_f32_t[nseg] for
+ * execute: the tile kernel (persistent waves) and the combine kernel on
+ * stream, no host work in between; out is twofold_f32_t[nseg] for
  * dtype 4 modes PLAIN/FAST/RIGOROUS, twofold_f64_t[nseg] otherwise; y must
  * be NULL for sums and given for dots (is_dot at creation). Capturable.
  * A plan must not execute on two streams at once. */

@@ -59,18 +59,14 @@ def _check_data(*ts):
 
 
 class Workspace:
-    """A prepared device workspace (twofold_workspace_init)."""
+    """Device scratch for the library's calls (no preparation needed)."""
 
     def __init__(self, nbytes, device):
         nbytes = max(256, int(nbytes))
         # 256-byte alignment: the caching allocator returns 512-byte blocks.
         self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.buf.data_ptr()
-        self.ptr = (base + 255) & ~255
+        self.ptr = (self.buf.data_ptr() + 255) & ~255
         self.nbytes = nbytes
-        check("twofold_workspace_init",
-              _lib.load().twofold_workspace_init(ctypes.c_void_p(self.ptr), nbytes,
-                                                 _stream_ptr(device)))
 
 
 _ws_cache = {}
@@ -78,7 +74,8 @@ _ws_cache = {}
 
 def workspace(nbytes, device):
     """The per-(device, stream) workspace, grown to at least nbytes. Calls on
-    one stream run in order, so they can share it."""
+    one stream run in order, so they can share it. (A graph captured on a
+    stream keeps using the workspace it was captured with.)"""
     device = torch.device(device)
     stream = torch.cuda.current_stream(device).cuda_stream
     key = (device.index, stream)

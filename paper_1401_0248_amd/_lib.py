@@ -35,7 +35,6 @@ SIGNATURES = {
     "twofold_default_launch": (_int, [_int, _int, _int, _int, _i64, _i64, _LP]),
     "twofold_workspace_bytes_single": (_sz, [_int, _int, _int, _i64, _LP]),
     "twofold_workspace_bytes_seg": (_sz, [_int, _int, _int, _i64, _i64, _LP]),
-    "twofold_workspace_init": (_int, [_vp, _sz, _vp]),
     "twofold_sum_f32": (_int, [_vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_sum_f64": (_int, [_vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_dot_f32": (_int, [_vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),

@@ -73,8 +73,7 @@ int resolve_single(int dtype, int is_dot, int mode, int64_t n, const twofold_lau
   } else {
     r.grid_blocks = 0;
   }
-  if (r.block_threads != 256 && r.block_threads != 512 && r.block_threads != 1024)
-    return TWOFOLD_EINVAL;
+  if (r.block_threads < 64 || r.block_threads > 1024 || r.block_threads % 64) return TWOFOLD_EINVAL;
   if (!valid_unroll(r.unroll)) return TWOFOLD_EINVAL;
   if (r.grid_blocks == 0) {
     const int64_t W = 16 / dtype;
@@ -110,20 +109,20 @@ int resolve_seg(int dtype, int is_dot, int mode, int64_t n_total, const twofold_
   return TWOFOLD_OK;
 }
 
+// Single vector: the GB block pairs (binary64) when GB > 1.
 size_t single_ws_bytes(const twofold_launch_t& lc) {
-  return kHdrBytes + align256(size_t(16) * size_t(lc.grid_blocks));
+  return align256(size_t(16) * size_t(lc.grid_blocks));
 }
 
 struct SegLayout {
-  size_t cnt_off, tbase_off, slots_off, total;
+  size_t tbase_off, slots_off, total;
 };
 
-// Device-offset path: [header][counters][tile table][tile pairs]. The
-// tiling kernel rewrites the counters and the table on every call.
+// Device-offset path: [status word][tile table][tile pairs]; the tiling
+// kernel rewrites the status and the table on every call.
 SegLayout seg_layout(int64_t nseg, int64_t max_tiles) {
   SegLayout L;
-  L.cnt_off = kHdrBytes;
-  L.tbase_off = L.cnt_off + align256(size_t(4) * size_t(nseg));
+  L.tbase_off = kHdrBytes;
   L.slots_off = L.tbase_off + align256(size_t(8) * size_t(nseg + 1));
   L.total = L.slots_off + align256(size_t(16) * size_t(max_tiles));
   return L;
@@ -145,37 +144,42 @@ int launch_status() {
 // ---- kernel dispatch ---------------------------------------------------------
 
 template <typename T, typename A, int M, bool DOT, bool YV>
-int launch_single_u(const T* x, const T* y, int64_t n, const twofold_launch_t& lc, uint32_t* hdr,
-                    double* part, void* out, hipStream_t st) {
+int launch_single_u(const T* x, const T* y, int64_t n, const twofold_launch_t& lc, double* part,
+                    void* out, hipStream_t st) {
   const dim3 grid(lc.grid_blocks), block(lc.block_threads);
   switch (lc.unroll) {
-    case 1: single_kernel<T, A, M, DOT, YV, 1><<<grid, block, 0, st>>>(x, y, n, hdr, part, out); break;
-    case 2: single_kernel<T, A, M, DOT, YV, 2><<<grid, block, 0, st>>>(x, y, n, hdr, part, out); break;
-    case 4: single_kernel<T, A, M, DOT, YV, 4><<<grid, block, 0, st>>>(x, y, n, hdr, part, out); break;
-    default: single_kernel<T, A, M, DOT, YV, 8><<<grid, block, 0, st>>>(x, y, n, hdr, part, out); break;
+    case 1: single_kernel<T, A, M, DOT, YV, 1><<<grid, block, 0, st>>>(x, y, n, part, out); break;
+    case 2: single_kernel<T, A, M, DOT, YV, 2><<<grid, block, 0, st>>>(x, y, n, part, out); break;
+    case 4: single_kernel<T, A, M, DOT, YV, 4><<<grid, block, 0, st>>>(x, y, n, part, out); break;
+    default: single_kernel<T, A, M, DOT, YV, 8><<<grid, block, 0, st>>>(x, y, n, part, out); break;
   }
-  return launch_status();
+  if (launch_status()) return TWOFOLD_EHIP;
+  if (lc.grid_blocks > 1) {
+    single_pass2_kernel<T, M><<<dim3(1), dim3(kPass2Lanes), 0, st>>>(part, lc.grid_blocks, out);
+    return launch_status();
+  }
+  return TWOFOLD_OK;
 }
 
 template <typename T, typename A, int M, bool DOT>
-int launch_single(const T* x, const T* y, int64_t n, const twofold_launch_t& lc, uint32_t* hdr,
-                  double* part, void* out, hipStream_t st) {
+int launch_single(const T* x, const T* y, int64_t n, const twofold_launch_t& lc, double* part,
+                  void* out, hipStream_t st) {
   if constexpr (DOT) {
     const bool yv = ((reinterpret_cast<uintptr_t>(y) - reinterpret_cast<uintptr_t>(x)) & 15u) == 0;
-    if (!yv) return launch_single_u<T, A, M, DOT, false>(x, y, n, lc, hdr, part, out, st);
+    if (!yv) return launch_single_u<T, A, M, DOT, false>(x, y, n, lc, part, out, st);
   }
-  return launch_single_u<T, A, M, DOT, true>(x, y, n, lc, hdr, part, out, st);
+  return launch_single_u<T, A, M, DOT, true>(x, y, n, lc, part, out, st);
 }
 
 template <typename T, typename A, int M, bool DOT, bool YV>
 int launch_seg_u(const T* x, const T* y, const int64_t* off, int64_t nseg, const int64_t* tbase,
-                 int check, const twofold_launch_t& lc, uint32_t* hdr, uint32_t* cnt, double* slots,
-                 void* out, hipStream_t st) {
+                 const uint32_t* status, const twofold_launch_t& lc, double* slots, void* out,
+                 hipStream_t st) {
   const dim3 grid(lc.grid_blocks), block(lc.block_threads);
   const int64_t ts = lc.tile_elems;
-#define TWOFOLD_SEG(UU)                                                                    \
-  seg_kernel<T, A, M, DOT, YV, UU><<<grid, block, 0, st>>>(x, y, off, nseg, tbase, ts, check, \
-                                                           hdr, cnt, slots, out)
+#define TWOFOLD_SEG(UU)                                                                       \
+  seg_kernel<T, A, M, DOT, YV, UU><<<grid, block, 0, st>>>(x, y, off, nseg, tbase, ts, status, \
+                                                           slots, out)
   switch (lc.unroll) {
     case 1: TWOFOLD_SEG(1); break;
     case 2: TWOFOLD_SEG(2); break;
@@ -183,54 +187,54 @@ int launch_seg_u(const T* x, const T* y, const int64_t* off, int64_t nseg, const
     default: TWOFOLD_SEG(8); break;
   }
 #undef TWOFOLD_SEG
+  if (launch_status()) return TWOFOLD_EHIP;
+  const int64_t blocks2 = (nseg + 3) / 4;  // one wave per segment, 4 waves per block
+  seg_pass2_kernel<T, M><<<dim3(unsigned(blocks2)), dim3(256), 0, st>>>(tbase, nseg, status, slots,
+                                                                        out);
   return launch_status();
 }
 
 template <typename T, typename A, int M, bool DOT>
 int launch_seg(const T* x, const T* y, const int64_t* off, int64_t nseg, const int64_t* tbase,
-               int check, const twofold_launch_t& lc, uint32_t* hdr, uint32_t* cnt, double* slots,
-               void* out, hipStream_t st) {
+               const uint32_t* status, const twofold_launch_t& lc, double* slots, void* out,
+               hipStream_t st) {
   if constexpr (DOT) {
     const bool yv = ((reinterpret_cast<uintptr_t>(y) - reinterpret_cast<uintptr_t>(x)) & 15u) == 0;
     if (!yv)
-      return launch_seg_u<T, A, M, DOT, false>(x, y, off, nseg, tbase, check, lc, hdr, cnt, slots,
-                                               out, st);
+      return launch_seg_u<T, A, M, DOT, false>(x, y, off, nseg, tbase, status, lc, slots, out, st);
   }
-  return launch_seg_u<T, A, M, DOT, true>(x, y, off, nseg, tbase, check, lc, hdr, cnt, slots, out,
-                                          st);
+  return launch_seg_u<T, A, M, DOT, true>(x, y, off, nseg, tbase, status, lc, slots, out, st);
 }
 
 // Mode switch for one data type. WIDE is only meaningful for binary32 data.
 template <typename T, bool DOT>
 int single_by_mode(int mode, const T* x, const T* y, int64_t n, const twofold_launch_t& lc,
-                   uint32_t* hdr, double* part, void* out, hipStream_t st) {
+                   double* part, void* out, hipStream_t st) {
   switch (mode) {
-    case kPlain: return launch_single<T, T, kPlain, DOT>(x, y, n, lc, hdr, part, out, st);
-    case kFast: return launch_single<T, T, kFast, DOT>(x, y, n, lc, hdr, part, out, st);
-    case kRigorous: return launch_single<T, T, kRigorous, DOT>(x, y, n, lc, hdr, part, out, st);
+    case kPlain: return launch_single<T, T, kPlain, DOT>(x, y, n, lc, part, out, st);
+    case kFast: return launch_single<T, T, kFast, DOT>(x, y, n, lc, part, out, st);
+    case kRigorous: return launch_single<T, T, kRigorous, DOT>(x, y, n, lc, part, out, st);
     default:
       if constexpr (sizeof(T) == 4)
-        return launch_single<T, double, kWide, DOT>(x, y, n, lc, hdr, part, out, st);
+        return launch_single<T, double, kWide, DOT>(x, y, n, lc, part, out, st);
       return TWOFOLD_EINVAL;
   }
 }
 
 template <typename T, bool DOT>
 int seg_by_mode(int mode, const T* x, const T* y, const int64_t* off, int64_t nseg,
-                const int64_t* tbase, int check, const twofold_launch_t& lc, uint32_t* hdr,
-                uint32_t* cnt, double* slots, void* out, hipStream_t st) {
+                const int64_t* tbase, const uint32_t* status, const twofold_launch_t& lc,
+                double* slots, void* out, hipStream_t st) {
   switch (mode) {
     case kPlain:
-      return launch_seg<T, T, kPlain, DOT>(x, y, off, nseg, tbase, check, lc, hdr, cnt, slots, out, st);
+      return launch_seg<T, T, kPlain, DOT>(x, y, off, nseg, tbase, status, lc, slots, out, st);
     case kFast:
-      return launch_seg<T, T, kFast, DOT>(x, y, off, nseg, tbase, check, lc, hdr, cnt, slots, out, st);
+      return launch_seg<T, T, kFast, DOT>(x, y, off, nseg, tbase, status, lc, slots, out, st);
     case kRigorous:
-      return launch_seg<T, T, kRigorous, DOT>(x, y, off, nseg, tbase, check, lc, hdr, cnt, slots, out,
-                                              st);
+      return launch_seg<T, T, kRigorous, DOT>(x, y, off, nseg, tbase, status, lc, slots, out, st);
     default:
       if constexpr (sizeof(T) == 4)
-        return launch_seg<T, double, kWide, DOT>(x, y, off, nseg, tbase, check, lc, hdr, cnt, slots,
-                                                 out, st);
+        return launch_seg<T, double, kWide, DOT>(x, y, off, nseg, tbase, status, lc, slots, out, st);
       return TWOFOLD_EINVAL;
   }
 }
@@ -249,11 +253,11 @@ int single_entry(const T* x, const T* y, int64_t n, int mode, const twofold_laun
   twofold_launch_t lc;
   const int rc = resolve_single(dtype, DOT, mode, n, launch, &lc);
   if (rc) return rc;
-  if (!ws || ws_bytes < single_ws_bytes(lc) || (reinterpret_cast<uintptr_t>(ws) & 255u))
+  if (lc.grid_blocks > 1 &&
+      (!ws || ws_bytes < single_ws_bytes(lc) || (reinterpret_cast<uintptr_t>(ws) & 255u)))
     return TWOFOLD_EWORKSPACE;
-  uint32_t* hdr = static_cast<uint32_t*>(ws);
-  double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + kHdrBytes);
-  return single_by_mode<T, DOT>(mode, x, y, n, lc, hdr, part, out, static_cast<hipStream_t>(stream));
+  return single_by_mode<T, DOT>(mode, x, y, n, lc, static_cast<double*>(ws), out,
+                                static_cast<hipStream_t>(stream));
 }
 
 template <typename T, bool DOT>
@@ -273,32 +277,27 @@ int seg_entry(const T* x, const T* y, int64_t n_total, const int64_t* off, int64
   const SegLayout L = seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems));
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255u)) return TWOFOLD_EWORKSPACE;
   char* base = static_cast<char*>(ws);
-  uint32_t* hdr = reinterpret_cast<uint32_t*>(base);
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(base + L.cnt_off);
+  uint32_t* status = reinterpret_cast<uint32_t*>(base);
   int64_t* tbase = reinterpret_cast<int64_t*>(base + L.tbase_off);
   double* slots = reinterpret_cast<double*>(base + L.slots_off);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  seg_tiles_kernel<<<1, 1024, 0, st>>>(off, nseg, n_total, lc.tile_elems, tbase, hdr, cnt);
+  seg_tiles_kernel<<<1, 1024, 0, st>>>(off, nseg, n_total, lc.tile_elems, tbase, status);
   if (launch_status()) return TWOFOLD_EHIP;
-  return seg_by_mode<T, DOT>(mode, x, y, off, nseg, tbase, 1, lc, hdr, cnt, slots, out, st);
+  return seg_by_mode<T, DOT>(mode, x, y, off, nseg, tbase, status, lc, slots, out, st);
 }
 
 }  // namespace
 
 // ---- plans -------------------------------------------------------------------
 
-// A plan owns the device copies of the offsets and of the tile table, and
-// its per-segment completion counters (zero at creation; every finishing
-// wave resets its segment's counter). The caller's workspace holds only the
-// header and the tile pairs, so no other call's use of that workspace can
-// leave a stale count behind for the plan.
+// A plan owns the device copies of the offsets and of the tile table; the
+// caller's workspace holds the tile pairs.
 struct twofold_seg_plan {
   int dtype, is_dot, mode;
   int64_t nseg, ntiles, n_total;
   twofold_launch_t lc;
   int64_t* d_off;
   int64_t* d_tbase;
-  uint32_t* d_cnt;
 };
 
 extern "C" {
@@ -326,16 +325,6 @@ size_t twofold_workspace_bytes_seg(int dtype, int is_dot, int mode, int64_t n_to
   twofold_launch_t lc;
   if (resolve_seg(dtype, is_dot != 0, mode, n_total, launch, &lc)) return 0;
   return seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems)).total;
-}
-
-int twofold_workspace_init(void* ws, size_t ws_bytes, void* stream) {
-  if (!ws || ws_bytes < kHdrBytes || (reinterpret_cast<uintptr_t>(ws) & 255u)) return TWOFOLD_EWORKSPACE;
-  const int64_t nwords = int64_t(ws_bytes / 4);
-  int64_t blocks = (nwords + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  ws_init_kernel<<<dim3(unsigned(blocks)), dim3(256), 0, static_cast<hipStream_t>(stream)>>>(
-      static_cast<uint32_t*>(ws), nwords);
-  return launch_status();
 }
 
 int twofold_sum_f32(const float* x, int64_t n, int mode, const twofold_launch_t* launch,
@@ -425,18 +414,14 @@ int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype
   p->n_total = n_total;
   p->lc = lc;
   const size_t bytes = sizeof(int64_t) * size_t(nseg + 1);
-  const size_t cnt_bytes = sizeof(uint32_t) * size_t(nseg > 0 ? nseg : 1);
   bool ok = hipMalloc(reinterpret_cast<void**>(&p->d_off), bytes) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&p->d_tbase), bytes) == hipSuccess &&
-            hipMalloc(reinterpret_cast<void**>(&p->d_cnt), cnt_bytes) == hipSuccess &&
             hipMemcpy(p->d_off, offsets_host, bytes, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(p->d_tbase, tb, bytes, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemset(p->d_cnt, 0, cnt_bytes) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+            hipMemcpy(p->d_tbase, tb, bytes, hipMemcpyHostToDevice) == hipSuccess;
   free(tb);
   if (!ok) {
     if (p->d_off) (void)hipFree(p->d_off);
     if (p->d_tbase) (void)hipFree(p->d_tbase);
-    if (p->d_cnt) (void)hipFree(p->d_cnt);
     free(p);
     return TWOFOLD_EHIP;
   }
@@ -446,7 +431,7 @@ int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype
 
 size_t twofold_seg_plan_workspace_bytes(const twofold_seg_plan_t* plan) {
   if (!plan) return 0;
-  return kHdrBytes + align256(size_t(16) * size_t(plan->ntiles));
+  return align256(size_t(16) * size_t(plan->ntiles > 0 ? plan->ntiles : 1));
 }
 
 int twofold_seg_plan_get_launch(const twofold_seg_plan_t* plan, twofold_launch_t* out) {
@@ -468,27 +453,24 @@ int twofold_seg_plan_execute(const twofold_seg_plan_t* plan, const void* x, cons
   if (!ws || ws_bytes < twofold_seg_plan_workspace_bytes(plan) ||
       (reinterpret_cast<uintptr_t>(ws) & 255u))
     return TWOFOLD_EWORKSPACE;
-  char* base = static_cast<char*>(ws);
-  uint32_t* hdr = reinterpret_cast<uint32_t*>(base);
-  uint32_t* cnt = plan->d_cnt;
-  double* slots = reinterpret_cast<double*>(base + kHdrBytes);
+  double* slots = static_cast<double*>(ws);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t* off = plan->d_off;
+  const int64_t* tb = plan->d_tbase;
+  const int64_t ns = plan->nseg;
+  const twofold_launch_t& lc = plan->lc;
   if (dtype == 4) {
     const float* xf = static_cast<const float*>(x);
     const float* yf = static_cast<const float*>(y);
     if (plan->is_dot)
-      return seg_by_mode<float, true>(plan->mode, xf, yf, plan->d_off, plan->nseg, plan->d_tbase, 0,
-                                      plan->lc, hdr, cnt, slots, out, st);
-    return seg_by_mode<float, false>(plan->mode, xf, yf, plan->d_off, plan->nseg, plan->d_tbase, 0,
-                                     plan->lc, hdr, cnt, slots, out, st);
+      return seg_by_mode<float, true>(plan->mode, xf, yf, off, ns, tb, nullptr, lc, slots, out, st);
+    return seg_by_mode<float, false>(plan->mode, xf, yf, off, ns, tb, nullptr, lc, slots, out, st);
   }
   const double* xd = static_cast<const double*>(x);
   const double* yd = static_cast<const double*>(y);
   if (plan->is_dot)
-    return seg_by_mode<double, true>(plan->mode, xd, yd, plan->d_off, plan->nseg, plan->d_tbase, 0,
-                                     plan->lc, hdr, cnt, slots, out, st);
-  return seg_by_mode<double, false>(plan->mode, xd, yd, plan->d_off, plan->nseg, plan->d_tbase, 0,
-                                    plan->lc, hdr, cnt, slots, out, st);
+    return seg_by_mode<double, true>(plan->mode, xd, yd, off, ns, tb, nullptr, lc, slots, out, st);
+  return seg_by_mode<double, false>(plan->mode, xd, yd, off, ns, tb, nullptr, lc, slots, out, st);
 }
 
 int twofold_seg_plan_destroy(twofold_seg_plan_t* plan) {
@@ -496,7 +478,6 @@ int twofold_seg_plan_destroy(twofold_seg_plan_t* plan) {
   int rc = TWOFOLD_OK;
   if (plan->d_off && hipFree(plan->d_off) != hipSuccess) rc = TWOFOLD_EHIP;
   if (plan->d_tbase && hipFree(plan->d_tbase) != hipSuccess) rc = TWOFOLD_EHIP;
-  if (plan->d_cnt && hipFree(plan->d_cnt) != hipSuccess) rc = TWOFOLD_EHIP;
   free(plan);
   return rc;
 }

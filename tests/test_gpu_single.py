@@ -14,7 +14,8 @@ from gpu_helpers import launch, pair, same_bits, to_dev
 pytestmark = pytest.mark.gpu
 
 SIZES = [0, 1, 3, 17, 1000, 4097, 65536 + 5, (1 << 20) + 3]
-LAUNCHES = [(256, 1, 1), (256, 4, 7), (512, 2, 3), (1024, 8, 5), (256, 4, 300)]
+LAUNCHES = [(256, 1, 1), (256, 4, 7), (512, 2, 3), (1024, 8, 5), (256, 4, 300), (64, 2, 2),
+            (128, 8, 33)]
 MODES = ["plain", "fast", "rigorous"]
 SHIFTS = [(0, 0), (1, 0), (3, 1), (2, 2)]
 
@@ -118,7 +119,7 @@ def test_graph_capture_replay():
     out_s = torch.empty(2, dtype=torch.float32, device=xd.device)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
-        wsd = tf.workspace(1 << 16, xd.device)  # prepared before capture, on this stream
+        wsd = tf.workspace(1 << 16, xd.device)  # allocated before capture
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
@@ -146,24 +147,27 @@ def test_nonfinite_propagates():
     assert v == np.inf
 
 
-def test_unprepared_workspace_gives_nan():
+def test_workspace_needs_no_preparation():
+    """Garbage in the workspace does not matter: every call writes what it
+    reads, and a one-block call does not touch the workspace at all."""
     x, _ = synth.uniform(1, 1 << 20, np.float64, count=2)
     xd, _ = to_dev(x)
+    ex = oracle.Exact(x)
 
     class Raw:
         pass
 
     raw = Raw()
-    buf = torch.zeros(1 << 20, dtype=torch.uint8, device=xd.device)  # not prepared
+    buf = torch.full((1 << 20,), 0xA5, dtype=torch.uint8, device=xd.device)
     raw.ptr = (buf.data_ptr() + 255) & ~255
     raw.nbytes = (1 << 20) - 256
-    v, e = pair(tf.sum(xd, "rigorous", ws=raw))
-    assert np.isnan(v) and np.isnan(e)
-    # a prepared one works and is left prepared
-    ex = oracle.Exact(x)
-    for _ in range(3):
-        v, e = pair(tf.sum(xd, "rigorous"))
+    for lc in (None, launch(64, 1, 1), launch(1024, 8, 9)):
+        v, e = pair(tf.sum(xd, "rigorous", lc, ws=raw))
         assert ex.diff(v, e) == 0.0
+    none = Raw()
+    none.ptr, none.nbytes = 0, 0
+    v, e = pair(tf.sum(xd, "rigorous", launch(256, 2, 1), ws=none))
+    assert ex.diff(v, e) == 0.0
 
 
 def test_hundred_hours_on_gpu():
