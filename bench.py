@@ -97,12 +97,177 @@ def oracle_leg(host, gpu):
     return base, acc
 
 
+COPY_BYTES = 1 << 28
+FORMS = ("plain", "fast", "rigorous")
+
+
+def graph_time(torch, calls, reps=5):
+    """Median seconds per call over `reps` replays of a graph of calls()."""
+    import statistics
+    calls()
+    torch.cuda.synchronize()
+    cap = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cap):
+        ncalls = calls()
+    g.replay()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        g.replay()
+        e1.record(st)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3 / ncalls)
+    return statistics.median(ts)
+
+
+def to_device_chunks(torch, chunks, n, dtype, dev):
+    t = torch.empty(n, dtype=dtype, device=dev)
+    i = 0
+    for c in chunks:
+        t[i:i + c.size].copy_(torch.from_numpy(c))
+        i += c.size
+    return t
+
+
+def roofline_sweep(torch, tf, dev):
+    """Every form (plain, fast, rigorous) of sum and dot, binary32 and
+    binary64, at N = 4096, 2^20 and 1 GiB per vector, uniform(-1, 1) data
+    of seed 1, tuned default launches, HIP-graph replay. One JSON line."""
+    import numpy as np
+    import synth
+
+    rows = []
+    for dtype, tdt in ((np.float32, torch.float32), (np.float64, torch.float64)):
+        size = np.dtype(dtype).itemsize
+        for n in (4096, 1 << 20, (1 << 30) // size):
+            log("sweep %s n=%d" % (np.dtype(dtype).name, n))
+            rng_chunks = synth.uniform_chunks(1, 2 * n, dtype)
+            both = to_device_chunks(torch, rng_chunks, 2 * n, tdt, dev)
+            x, y = both[:n], both[n:]  # x drawn entirely, then y
+            reps = 1 if n * size >= (1 << 28) else 50
+            for op in ("sum", "dot"):
+                for form in FORMS + (("wide",) if dtype == np.float32 else ()):
+                    out = torch.empty(2, dtype=torch.float64, device=dev)
+                    o = out if (size == 8 or form == "wide") else out.view(torch.float32)[:2]
+                    need = tf._lib.load().twofold_workspace_bytes_single(
+                        size, op == "dot", tf.mode_id(form), n, None)
+                    ws = tf.Workspace(need, dev)
+
+                    def calls():
+                        for _ in range(reps):
+                            if form == "wide":
+                                (tf.dotd(x, y, out=o, ws=ws) if op == "dot"
+                                 else tf.sumd(x, out=o, ws=ws))
+                            elif op == "dot":
+                                tf.dot(x, y, form, out=o, ws=ws)
+                            else:
+                                tf.sum(x, form, out=o, ws=ws)
+                        return reps
+
+                    t = graph_time(torch, calls)
+                    nbytes = n * size * (2 if op == "dot" else 1)
+                    rows.append({"dtype": np.dtype(dtype).name, "op": op, "form": form, "n": n,
+                                 "us": round(t * 1e6, 3), "gelem_s": round(n / t / 1e9, 2),
+                                 "gb_s": round(nbytes / t / 1e9, 1),
+                                 "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4)})
+                    log("  %s %-8s %8.2f us %8.1f GB/s" % (op, form, t * 1e6, nbytes / t / 1e9))
+            del both, x, y
+            torch.cuda.empty_cache()
+    print(json.dumps({"workload": "roofline sweep, uniform(-1,1) seed 1, tuned default launches",
+                      "peak_gb_s": HBM_PEAK_GBS, "rows": rows}), flush=True)
+
+
+def segmented_batch(torch, tf, dev):
+    """20,000 segment pairs with log-uniform lengths in [1, 2^20] (seed 3,
+    1,504,333,896 elements), uniform(-1, 1) data of seed 3 (x, then y),
+    binary32 and binary64, fast and rigorous dots through plans with the
+    tuned default launch, HIP-graph replay. One JSON line."""
+    import numpy as np
+    import synth
+
+    lengths = synth.segment_lengths(3, 20000)
+    off = synth.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    rows = []
+    for dtype, tdt in ((np.float32, torch.float32), (np.float64, torch.float64)):
+        log("segmented %s: generating %d x 2 values" % (np.dtype(dtype).name, n))
+        both = to_device_chunks(torch, synth.uniform_chunks(3, 2 * n, dtype), 2 * n, tdt, dev)
+        x, y = both[:n], both[n:]
+        for form in ("fast", "rigorous"):
+            plan = tf.SegPlan(off, tdt, True, form)
+            out = torch.empty((plan.nseg, 2), dtype=plan.out_dtype, device=dev)
+            ws = tf.Workspace(plan.workspace_bytes, dev)
+            t = graph_time(torch, lambda: (plan.execute(x, y, out=out, ws=ws), 1)[1])
+            nbytes = 2 * n * np.dtype(dtype).itemsize
+            rows.append({"dtype": np.dtype(dtype).name, "form": form, "nseg": int(plan.nseg),
+                         "elements": n, "ms": round(t * 1e3, 4), "gelem_s": round(n / t / 1e9, 1),
+                         "gb_s": round(nbytes / t / 1e9, 1),
+                         "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
+                         "launch": plan.launch.as_dict()})
+            log("  %s %s %.3f ms %.1f GB/s" % (np.dtype(dtype).name, form, t * 1e3, nbytes / t / 1e9))
+            plan.close()
+        del both, x, y
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "segmented twofold dot, 20,000 log-uniform segments in "
+                                  "[1, 2^20], seed 3", "peak_gb_s": HBM_PEAK_GBS, "rows": rows}),
+          flush=True)
+
+
+def calibrate_copy(torch, dev):
+    """A plain device copy of 256 MiB, five times: its FETCH_SIZE and
+    WRITE_SIZE counters per dispatch calibrate the ones of the reductions."""
+    a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).uniform_(-1, 1)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read": COPY_BYTES,
+                      "bytes_written": COPY_BYTES, "dispatches": 5}), flush=True)
+
+
+KERNEL_SOURCES = ("eft.hpp", "kernels.hpp", "twofold.hip", "tuned_table.inc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_f64_rigorous_dot_n2e24.json")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1401_0248_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per dominant call from the committed counter summary, or
+    None if the kernels changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return t.get("traffic_bytes_per_call")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--workload", choices=("illcond", "sweep", "segmented"), default="illcond",
+                    help="illcond: the headline line (default); sweep: the roofline sweep of "
+                         "every form at 4096, 2^20 and 1 GiB per vector; segmented: the "
+                         "20,000-segment batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library's reduction runs on one device "
@@ -115,6 +280,15 @@ def main():
     import paper_1401_0248_amd as tf
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        calibrate_copy(torch, dev)
+        return
+    if args.workload == "sweep":
+        roofline_sweep(torch, tf, dev)
+        return
+    if args.workload == "segmented":
+        segmented_batch(torch, tf, dev)
+        return
     log("generating 12 ill-conditioned pairs, N=2^24")
     t0 = time.perf_counter()
     host = make_inputs()
@@ -130,25 +304,41 @@ def main():
                    L.twofold_workspace_bytes_single(4, 1, 2, N, None))
     ws = tf.Workspace(ws_bytes, dev)
 
-    # One step as two HIP graphs on one stream: A = the binary64 rigorous
-    # dots (the dominant kernel, bracketed by events), B = the binary32
-    # rigorous dots, then all fast dots. Between two reads of one pair about
-    # 2 GiB of other pairs are read, so the pair is not served from cache.
+    # One step as two HIP graphs: A = the binary64 rigorous dots, one after
+    # the other (the dominant kernel, bracketed by events), B = the binary32
+    # rigorous and fast dots on one branch, the binary64 fast dots on a
+    # second. Between two reads of one pair at least 1 GiB of other pairs is
+    # read, so no pair is served from the 256 MB last-level cache.
     def calls(keys, mode):
         for k in keys:
             xd, yd = dev_in[k]
             tf.dot(xd, yd, mode, out=outs[(k, mode)], ws=ws)
 
     cap = torch.cuda.Stream(dev)
+    side = torch.cuda.Stream(dev)
+    ws2 = tf.Workspace(ws_bytes, dev)
+
+    def calls_on(keys, mode, w):
+        for k in keys:
+            xd, yd = dev_in[k]
+            tf.dot(xd, yd, mode, out=outs[(k, mode)], ws=w)
+
     calls(f64 + f32, "rigorous")  # eager run first: loads the library, checks the calls
     calls(f64 + f32, "fast")
     torch.cuda.synchronize()
     gA, gB = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
     with torch.cuda.graph(gA, stream=cap):
         calls(f64, "rigorous")
+    # B runs as two independent branches (fork/join inside the capture), each
+    # with its own workspace, so one branch's 1-block combine kernels and the
+    # ramp-down of its reductions overlap the other branch's streaming.
     with torch.cuda.graph(gB, stream=cap):
-        calls(f32, "rigorous")
-        calls(f64 + f32, "fast")
+        side.wait_stream(cap)
+        calls_on(f32, "rigorous", ws)
+        calls_on(f32, "fast", ws)
+        with torch.cuda.stream(side):
+            calls_on(f64, "fast", ws2)
+        cap.wait_stream(side)
     stream = torch.cuda.current_stream(dev)
     ev = []
 
@@ -195,7 +385,8 @@ def main():
                                "HIP-graph replay)",
                    "n": N, "pairs": len(dev_in), "dots_per_step": ndots},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(),
                      "kernel": "binary64 rigorous twofold dot (single_kernel + single_pass2_kernel)",
                      "launch": lc.as_dict(), "bytes_per_launch": bytes_launch,
                      "avg_launch_us": round(avg * 1e6, 2)},

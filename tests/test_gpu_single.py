@@ -84,7 +84,13 @@ def test_value_equals_plain(dtype):
     x, y = synth.uniform(77, (1 << 20) + 9, dtype, count=2)
     xd, _ = to_dev(x, 1)
     yd, _ = to_dev(y, 2)
-    for lc in (None, launch(512, 8, 64)):
+    n = x.size
+    # the tuned default of each form, and one explicit shape; the invariant
+    # holds for one launch shape shared by the plain and the twofold call
+    shapes = [tf.default_launch(0, np.dtype(dtype).itemsize, dot, mode, n)
+              for dot in (False, True) for mode in ("fast", "rigorous")]
+    shapes.append(launch(512, 8, 64))
+    for lc in shapes:
         ps = pair(tf.sum(xd, "plain", lc))
         pd = pair(tf.dot(xd, yd, "plain", lc))
         assert ps[1] == 0.0 and pd[1] == 0.0
