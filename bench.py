@@ -135,9 +135,12 @@ def to_device_chunks(torch, chunks, n, dtype, dev):
 
 
 def roofline_sweep(torch, tf, dev):
-    """Every form (plain, fast, rigorous) of sum and dot, binary32 and
-    binary64, at N = 4096, 2^20 and 1 GiB per vector, uniform(-1, 1) data
-    of seed 1, tuned default launches, HIP-graph replay. One JSON line."""
+    """Every form of sum and dot (plain, fast, rigorous, Kahan, the wide
+    accumulator for binary32 data, and for dots the paper's rounded-product
+    fast and rigorous forms), binary32 and binary64, at N = 4096, 2^20 and
+    1 GiB per vector, uniform(-1, 1) data of seed 1, tuned default
+    launches, HIP-graph replay: the method comparison of the paper's
+    Table 1 on one MI355X. One JSON line."""
     import numpy as np
     import synth
 
@@ -151,7 +154,10 @@ def roofline_sweep(torch, tf, dev):
             x, y = both[:n], both[n:]  # x drawn entirely, then y
             reps = 1 if n * size >= (1 << 28) else 50
             for op in ("sum", "dot"):
-                for form in FORMS + (("wide",) if dtype == np.float32 else ()):
+                forms = FORMS + ("kahan",) + (("wide",) if dtype == np.float32 else ())
+                if op == "dot":
+                    forms += ("fast_rounded", "rigorous_rounded")
+                for form in forms:
                     out = torch.empty(2, dtype=torch.float64, device=dev)
                     o = out if (size == 8 or form == "wide") else out.view(torch.float32)[:2]
                     need = tf._lib.load().twofold_workspace_bytes_single(
@@ -230,7 +236,7 @@ def calibrate_copy(torch, dev):
                       "bytes_written": COPY_BYTES, "dispatches": 5}), flush=True)
 
 
-KERNEL_SOURCES = ("eft.hpp", "kernels.hpp", "twofold.hip", "tuned_table.inc")
+KERNEL_SOURCES = ("eft.hpp", "kernels.hpp", "host_common.hpp", "twofold.hip", "tuned_table.inc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_f64_rigorous_dot_n2e24.json")
 
 

@@ -17,6 +17,12 @@
  *   TWOFOLD_RIGOROUS  rigorous twofold step built on Knuth's two-sum
  *                     (Theorem 2, Example 3): every step's round-off is
  *                     captured exactly.
+ *   TWOFOLD_KAHAN     compensated summation (Example 2): value is the
+ *                     compensated sum, error the correction still pending
+ *                     (-c); pairs are combined like twofold pairs.
+ *   TWOFOLD_FAST_ROUNDED, TWOFOLD_RIGOROUS_ROUNDED  dots only: the paper's
+ *                     own dot rule, the rounded product as the item and its
+ *                     rounding not tracked (same value as the FMA forms).
  * Dot products: the paper substitutes the rounded product a[i]*b[i] for the
  * data item (end of "Algorithms"). This library also captures the product's
  * rounding: p = fl(x*y), pi = fma(x, y, -p), x*y = p + pi exactly unless the
@@ -33,7 +39,9 @@
  * T is float or double, W = 16/sizeof(T) (elements per 16-byte vector).
  * Every chain starts at (+0, +0). combine((s1,e1),(s2,e2)) is two-sum
  * (Theorem 2, all six operations) of s1, s2 giving (x, y), then
- * error (e1 + e2) + y, value x; in plain mode it is (s1 + s2, +0).
+ * error (e1 + e2) + y, value x; in plain and wide modes it is
+ * (s1 + s2, +0). The Kahan step keeps e = -c: yk = item + e, t = s + yk,
+ * e = yk - (t - s), s = t (exactly Example 2's operations, negated).
  * Single vector, launch (block_threads BT, unroll U, grid_blocks GB),
  * L = GB*BT lanes, lane g = block*BT + thread:
  *   1. head: the h = min(n, elements before x's first 16-byte boundary)
@@ -53,7 +61,7 @@
  *      then steps 5 and 6 over those 256 lanes;
  *   8. finalize R = (V, E): binary64 results are (V, E); binary32 results
  *      are value fl32(V) and error fl32((V - value) + E), in binary64
- *      (V - value is exact); plain binary32 has error +0.
+ *      (V - value is exact); plain and wide results have error +0.
  * Segmented, launch (block_threads, unroll U, grid_blocks, tile_elems TS):
  *   segment s covers elements [off[s], off[s+1]) and has ceil(len/TS)
  *   tiles; tile j covers [off[s] + j*TS, min(off[s+1], off[s] + (j+1)*TS));
@@ -107,7 +115,10 @@ enum {
   TWOFOLD_PLAIN = 0,
   TWOFOLD_FAST = 1,
   TWOFOLD_RIGOROUS = 2,
-  TWOFOLD_WIDE = 3 /* binary32 data, binary64 accumulator (segmented plans) */
+  TWOFOLD_WIDE = 3, /* binary32 data, binary64 accumulator (sumd/dotd, plans) */
+  TWOFOLD_KAHAN = 4,
+  TWOFOLD_FAST_ROUNDED = 5,
+  TWOFOLD_RIGOROUS_ROUNDED = 6
 };
 
 enum {

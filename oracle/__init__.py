@@ -24,8 +24,9 @@ import numpy as np
 
 from . import build as _build
 
-PLAIN, FAST, RIGOROUS, WIDE = 0, 1, 2, 3
-MODES = {"plain": PLAIN, "fast": FAST, "rigorous": RIGOROUS, "wide": WIDE}
+PLAIN, FAST, RIGOROUS, WIDE, KAHAN, FAST_ROUNDED, RIGOROUS_ROUNDED = 0, 1, 2, 3, 4, 5, 6
+MODES = {"plain": PLAIN, "fast": FAST, "rigorous": RIGOROUS, "wide": WIDE, "kahan": KAHAN,
+         "fast_rounded": FAST_ROUNDED, "rigorous_rounded": RIGOROUS_ROUNDED}
 
 _lib = None
 
@@ -54,7 +55,7 @@ def lib():
                 f = getattr(L, "oracle_%s_%s" % (nm, sfx))
                 f.restype = ct
                 f.argtypes = [vp, i64]
-            for nm in ("sumtf", "sumt"):
+            for nm in ("sumtf", "sumt", "sumk_pair"):
                 f = getattr(L, "oracle_%s_%s" % (nm, sfx))
                 f.restype = None
                 f.argtypes = [vp, i64, vp]
@@ -62,7 +63,7 @@ def lib():
                 f = getattr(L, "oracle_%s_%s" % (nm, sfx))
                 f.restype = ct
                 f.argtypes = [vp, vp, i64]
-            for nm in ("dottf_rounded", "dott_rounded", "dottf", "dott"):
+            for nm in ("dottf_rounded", "dott_rounded", "dottf", "dott", "dotk_pair"):
                 f = getattr(L, "oracle_%s_%s" % (nm, sfx))
                 f.restype = None
                 f.argtypes = [vp, vp, i64, vp]
@@ -159,7 +160,7 @@ def seq(kind, x, y=None):
         t = np.float64 if kind == "dotd" else x.dtype.type
         return t(v), t(0)
     out = np.zeros(2, dtype=x.dtype)
-    if kind in ("sumtf", "sumt"):
+    if kind in ("sumtf", "sumt", "sumk_pair"):
         f(_ptr(x), x.size, _ptr(out))
     else:
         f(_ptr(x), _ptr(y), x.size, _ptr(out))

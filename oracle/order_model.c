@@ -21,7 +21,8 @@
  *      widened to binary64, go to 256 lanes (lane l takes l, l+256, ... in
  *      order, starting from +0), then steps 5 and 6 in binary64;
  *   8. finalize: binary64 results as they are; binary32 value fl32(V) and
- *      error fl32((V - value) + E), both operations in binary64.
+ *      error fl32((V - value) + E), both operations in binary64 (error +0
+ *      for the plain and wide modes, whose pairs carry no error).
  * Segmented, tiles of TS elements (TS a multiple of 64*W): segment s has
  * ceil(len_s/TS) tiles; each tile is reduced by one 64-lane wave with
  * steps 1-5 on the tile's range; a one-tile segment's pair is finalized
@@ -39,9 +40,13 @@
 #define MODE_FAST 1
 #define MODE_RIGOROUS 2
 #define MODE_WIDE 3
+#define MODE_KAHAN 4
+#define MODE_FAST_ROUNDED 5
+#define MODE_RIGOROUS_ROUNDED 6
+#define HAS_ERROR(m) ((m) != MODE_PLAIN && (m) != MODE_WIDE)
 
 static void combine64(int mode, double* s1, double* e1, double s2, double e2) {
-  if (mode == MODE_PLAIN || mode == MODE_WIDE) {
+  if (!HAS_ERROR(mode)) {
     *s1 = *s1 + s2;
     *e1 = 0;
     return;
@@ -98,7 +103,7 @@ static void finalize(int mode, int tsize, double V, double E, double* out2) {
   }
   float v = (float)V;
   float e = 0.0f;
-  if (mode != MODE_PLAIN) {
+  if (HAS_ERROR(mode)) {
     double rest = V - (double)v; /* exact: V and v share their leading bits */
     e = (float)(rest + E);
   }
@@ -137,10 +142,11 @@ static void finalize(int mode, int tsize, double V, double E, double* out2) {
 #undef FMA_T
 #undef NAME
 
-static int valid_common(int dtype, int mode, int U) {
+static int valid_common(int dtype, int mode, int is_dot, int U) {
   if (dtype != 4 && dtype != 8) return 0;
-  if (mode < MODE_PLAIN || mode > MODE_WIDE) return 0;
+  if (mode < MODE_PLAIN || mode > MODE_RIGOROUS_ROUNDED) return 0;
   if (mode == MODE_WIDE && dtype != 4) return 0;
+  if ((mode == MODE_FAST_ROUNDED || mode == MODE_RIGOROUS_ROUNDED) && !is_dot) return 0;
   if (U < 1 || U > 64) return 0;
   return 1;
 }
@@ -148,7 +154,7 @@ static int valid_common(int dtype, int mode, int U) {
 int oracle_model_single(int dtype, int mode, const void* x, const void* y, int64_t n,
                         int x_misalign, int block_threads, int unroll, int grid_blocks,
                         double* out2) {
-  if (!valid_common(dtype, mode, unroll) || n < 0 || !x) return -1;
+  if (!valid_common(dtype, mode, y != NULL, unroll) || n < 0 || (!x && n > 0)) return -1;
   if (block_threads < 64 || block_threads > 1024 || block_threads % 64) return -1;
   if (grid_blocks < 1 || (int64_t)grid_blocks * block_threads > ((int64_t)1 << 26)) return -1;
   if (x_misalign < 0 || x_misalign >= 16 / dtype) return -1;
@@ -166,7 +172,7 @@ int oracle_model_single(int dtype, int mode, const void* x, const void* y, int64
 int oracle_model_seg(int dtype, int mode, const void* x, const void* y,
                      const int64_t* offsets, int64_t nseg, int x_misalign,
                      int unroll, int64_t tile_elems, double* out) {
-  if (!valid_common(dtype, mode, unroll) || nseg < 0 || !offsets) return -1;
+  if (!valid_common(dtype, mode, y != NULL, unroll) || nseg < 0 || !offsets) return -1;
   if (tile_elems <= 0 || tile_elems % (64 * (16 / dtype))) return -1;
   if (x_misalign < 0 || x_misalign >= 16 / dtype) return -1;
   if (nseg > 0 && offsets[0] < 0) return -1;

@@ -56,11 +56,13 @@ int    oracle_xacc_sign(const void* acc);
  * out2 receives {value, error}. Functions without out2 return the sum.    */
 float  oracle_sum_f32(const float* x, int64_t n);
 float  oracle_sumk_f32(const float* x, int64_t n);
+void   oracle_sumk_pair_f32(const float* x, int64_t n, float* out2);
 void   oracle_sumtf_f32(const float* x, int64_t n, float* out2);
 void   oracle_sumt_f32(const float* x, int64_t n, float* out2);
 double oracle_sumd_f32(const float* x, int64_t n);
 float  oracle_dot_f32(const float* x, const float* y, int64_t n);
 float  oracle_dotk_f32(const float* x, const float* y, int64_t n);
+void   oracle_dotk_pair_f32(const float* x, const float* y, int64_t n, float* out2);
 void   oracle_dottf_rounded_f32(const float* x, const float* y, int64_t n, float* out2);
 void   oracle_dott_rounded_f32(const float* x, const float* y, int64_t n, float* out2);
 void   oracle_dottf_f32(const float* x, const float* y, int64_t n, float* out2);
@@ -69,10 +71,12 @@ double oracle_dotd_f32(const float* x, const float* y, int64_t n);
 
 double oracle_sum_f64(const double* x, int64_t n);
 double oracle_sumk_f64(const double* x, int64_t n);
+void   oracle_sumk_pair_f64(const double* x, int64_t n, double* out2);
 void   oracle_sumtf_f64(const double* x, int64_t n, double* out2);
 void   oracle_sumt_f64(const double* x, int64_t n, double* out2);
 double oracle_dot_f64(const double* x, const double* y, int64_t n);
 double oracle_dotk_f64(const double* x, const double* y, int64_t n);
+void   oracle_dotk_pair_f64(const double* x, const double* y, int64_t n, double* out2);
 void   oracle_dottf_rounded_f64(const double* x, const double* y, int64_t n, double* out2);
 void   oracle_dott_rounded_f64(const double* x, const double* y, int64_t n, double* out2);
 void   oracle_dottf_f64(const double* x, const double* y, int64_t n, double* out2);
@@ -80,7 +84,10 @@ void   oracle_dott_f64(const double* x, const double* y, int64_t n, double* out2
 
 /* ---- 3. order model --------------------------------------------------------
  * mode: 0 plain, 1 fast, 2 rigorous, 3 wide (binary32 data, binary64
- * accumulator; paper's sumd/dotd). dtype: 4 (binary32) or 8 (binary64).
+ * accumulator; paper's sumd/dotd), 4 Kahan (Example 2; the error is the
+ * negated correction), 5 fast and 6 rigorous with the rounded product as
+ * the item (the paper's dot rule; dots only). dtype: 4 (binary32) or 8
+ * (binary64).
  * y == NULL selects the sum, otherwise the dot.
  * x_misalign: (address of x modulo 16) / dtype, i.e. where x starts inside
  * its 16-byte line, in elements (0 .. 16/dtype - 1). The head of a range

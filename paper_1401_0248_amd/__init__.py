@@ -14,15 +14,17 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import FAST, PLAIN, RIGOROUS, WIDE, Launch, TwofoldError, check
+from ._lib import (FAST, FAST_ROUNDED, KAHAN, PLAIN, RIGOROUS, RIGOROUS_ROUNDED, WIDE, Launch,
+                   TwofoldError, check)
 
 __all__ = [
     "sum", "dot", "sumd", "dotd", "segsum", "segdot", "SegPlan", "Launch",
     "TwofoldError", "workspace", "default_launch", "probe_read", "probe_compute",
-    "PLAIN", "FAST", "RIGOROUS", "WIDE", "mode_id",
+    "PLAIN", "FAST", "RIGOROUS", "WIDE", "KAHAN", "FAST_ROUNDED", "RIGOROUS_ROUNDED", "mode_id",
 ]
 
-_MODES = {"plain": PLAIN, "fast": FAST, "rigorous": RIGOROUS, "wide": WIDE}
+_MODES = {"plain": PLAIN, "fast": FAST, "rigorous": RIGOROUS, "wide": WIDE, "kahan": KAHAN,
+          "fast_rounded": FAST_ROUNDED, "rigorous_rounded": RIGOROUS_ROUNDED}
 
 
 def mode_id(mode):

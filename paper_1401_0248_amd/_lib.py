@@ -10,7 +10,7 @@ import os
 from . import build as _build
 
 OK, EINVAL, EWORKSPACE, EHIP, EALIGN, EOFFSETS = 0, -1, -2, -3, -4, -5
-PLAIN, FAST, RIGOROUS, WIDE = 0, 1, 2, 3
+PLAIN, FAST, RIGOROUS, WIDE, KAHAN, FAST_ROUNDED, RIGOROUS_ROUNDED = 0, 1, 2, 3, 4, 5, 6
 
 # Every symbol the public header declares, with (restype, argtypes).
 _vp = ctypes.c_void_p

@@ -13,7 +13,20 @@
 
 namespace twofold {
 
-enum Mode : int { kPlain = 0, kFast = 1, kRigorous = 2, kWide = 3 };
+// kKahan: Example 2; kFastRounded / kRigorousRounded: the paper's own dot
+// rule (the rounded product is the item; its rounding is not tracked).
+enum Mode : int {
+  kPlain = 0,
+  kFast = 1,
+  kRigorous = 2,
+  kWide = 3,
+  kKahan = 4,
+  kFastRounded = 5,
+  kRigorousRounded = 6
+};
+
+// Modes whose pairs carry an error (all but plain and wide).
+constexpr bool has_error(int m) { return m != kPlain && m != kWide; }
 
 __device__ __forceinline__ float fma_rn(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_rn(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -29,14 +42,25 @@ __device__ __forceinline__ void step(A& s, A& e, T xv, T yv) {
   } else if constexpr (M == kPlain) {
     T item = DOT ? xv * yv : xv;
     s = s + item;
+  } else if constexpr (M == kKahan) {
+    // Example 2 with e holding -c, the negated correction: item - c is
+    // item + e and the new -c is yk - (t - s), both exactly the negations
+    // of the paper's operations.
+    T item = DOT ? xv * yv : xv;
+    T yk = item + e;
+    T t = s + yk;
+    e = yk - (t - s);
+    s = t;
   } else {
+    constexpr bool kTrack = DOT && (M == kFast || M == kRigorous);  // FMA remainder
+    constexpr bool kFastForm = (M == kFast || M == kFastRounded);
     T p = DOT ? xv * yv : xv;
     T t = s + p;
-    if constexpr (M == kFast) {
+    if constexpr (kFastForm) {
       // Example 1: c = (t - s) - item is the negated round-off of s + item
       // when |s| >= |item| (Theorem 1).
       T c = (t - s) - p;
-      if constexpr (DOT) {
+      if constexpr (kTrack) {
         T pi = fma_rn(xv, yv, -p);  // x*y - p, exact
         e = e + (pi - c);
       } else {
@@ -48,7 +72,7 @@ __device__ __forceinline__ void step(A& s, A& e, T xv, T yv) {
       T yt = t - s;
       T dy = p - yt;
       T ds = s - (t - yt);
-      if constexpr (DOT) {
+      if constexpr (kTrack) {
         T pi = fma_rn(xv, yv, -p);
         e = e + ((ds + dy) + pi);
       } else {
@@ -64,7 +88,7 @@ __device__ __forceinline__ void step(A& s, A& e, T xv, T yv) {
 // pairs carry no error.
 template <int M, typename A>
 __device__ __forceinline__ void combine(A& s1, A& e1, A s2, A e2) {
-  if constexpr (M == kPlain || M == kWide) {
+  if constexpr (!has_error(M)) {
     s1 = s1 + s2;
     e1 = A(0);
   } else {
@@ -115,7 +139,7 @@ __device__ __forceinline__ double xor_lane(double v) {
 template <int M, int D, typename A>
 __device__ __forceinline__ void wave_stage(A& s, A& e) {
   const A s2 = xor_lane<D>(s);
-  if constexpr (M == kPlain || M == kWide) {
+  if constexpr (!has_error(M)) {
     combine<M>(s, e, s2, A(0));
   } else {
     const A e2 = xor_lane<D>(e);

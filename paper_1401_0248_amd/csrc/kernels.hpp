@@ -156,7 +156,7 @@ __device__ __forceinline__ void finalize_store(void* __restrict__ out, int64_t i
   } else {
     const float v = static_cast<float>(V);
     float e = 0.0f;
-    if constexpr (M != kPlain) e = static_cast<float>((V - static_cast<double>(v)) + E);
+    if constexpr (has_error(M)) e = static_cast<float>((V - static_cast<double>(v)) + E);
     reinterpret_cast<float2*>(out)[idx] = make_float2(v, e);
   }
 }
@@ -313,45 +313,6 @@ seg_pass2_kernel(const int64_t* __restrict__ tbase, int64_t nseg,
   }
   wave_combine<M>(qs, qe);
   if (lane == 0) finalize_store<T, M>(out, sg, qs, qe);
-}
-
-// Tile table from device offsets (one block of 1024 threads), rows of 1024
-// segments: tiles per segment, block-wide exclusive scan, running carry.
-// Also records in *status whether the offsets are valid (offsets[0] >= 0,
-// non-decreasing, offsets[nseg] <= n_total).
-__global__ void __launch_bounds__(1024)
-seg_tiles_kernel(const int64_t* __restrict__ off, int64_t nseg, int64_t n_total, int64_t TS,
-                 int64_t* __restrict__ tbase, uint32_t* __restrict__ status) {
-  __shared__ int64_t sh[1024];
-  __shared__ int sh_bad;
-  const int t = threadIdx.x;
-  if (t == 0) sh_bad = (off[0] < 0 || off[nseg] > n_total) ? 1 : 0;
-  __syncthreads();
-  int64_t carry = 0;
-  for (int64_t base = 0; base < nseg; base += 1024) {
-    const int64_t sg = base + t;
-    int64_t tiles = 0;
-    if (sg < nseg) {
-      const int64_t len = off[sg + 1] - off[sg];
-      if (len < 0) sh_bad = 1;  // benign race: every writer stores 1
-      tiles = len > 0 ? (len + TS - 1) / TS : 0;
-    }
-    sh[t] = tiles;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
-      const int64_t v = t >= d ? sh[t - d] : 0;
-      __syncthreads();
-      sh[t] += v;
-      __syncthreads();
-    }
-    if (sg < nseg) tbase[sg] = carry + sh[t] - tiles;
-    carry += sh[1023];
-    __syncthreads();
-  }
-  if (t == 0) {
-    tbase[nseg] = carry;
-    *status = sh_bad ? 1u : 0u;
-  }
 }
 
 }  // namespace twofold

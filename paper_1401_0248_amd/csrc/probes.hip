@@ -115,9 +115,17 @@ int compute_by_mode(int mode, const void* seed, int64_t iters, const twofold_lau
     case kPlain: return launch_compute<T, T, kPlain, DOT>(seed, iters, lc, sink, st);
     case kFast: return launch_compute<T, T, kFast, DOT>(seed, iters, lc, sink, st);
     case kRigorous: return launch_compute<T, T, kRigorous, DOT>(seed, iters, lc, sink, st);
-    default:
+    case kKahan: return launch_compute<T, T, kKahan, DOT>(seed, iters, lc, sink, st);
+    case kFastRounded:
+      if constexpr (DOT) return launch_compute<T, T, kFastRounded, DOT>(seed, iters, lc, sink, st);
+      return TWOFOLD_EINVAL;
+    case kRigorousRounded:
+      if constexpr (DOT) return launch_compute<T, T, kRigorousRounded, DOT>(seed, iters, lc, sink, st);
+      return TWOFOLD_EINVAL;
+    case kWide:
       if constexpr (sizeof(T) == 4) return launch_compute<T, double, kWide, DOT>(seed, iters, lc, sink, st);
       return TWOFOLD_EINVAL;
+    default: return TWOFOLD_EINVAL;
   }
 }
 
@@ -160,7 +168,9 @@ int twofold_probe_compute(int dtype, int is_dot, int mode, const void* seed, int
                           const twofold_launch_t* launch, double* sink, void* stream) {
   if (!seed || !sink || iters < 0 || !launch_ok(launch)) return TWOFOLD_EINVAL;
   if (dtype != 4 && dtype != 8) return TWOFOLD_EINVAL;
-  if (mode < kPlain || mode > kWide || (mode == kWide && dtype != 4)) return TWOFOLD_EINVAL;
+  if (mode < kPlain || mode > kRigorousRounded || (mode == kWide && dtype != 4) ||
+      ((mode == kFastRounded || mode == kRigorousRounded) && !is_dot))
+    return TWOFOLD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(seed) % uintptr_t(dtype)) || (reinterpret_cast<uintptr_t>(sink) & 7u))
     return TWOFOLD_EALIGN;
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -1,0 +1,292 @@
+// segmented.hip: host side of the segmented (CSR batch) entry points of
+// include/twofold.h: device-offset calls and plans.
+//
+// Device-offset calls run three kernels (tiling, tiles, per-segment
+// combine); plan executes run the last two, with the tile table built once
+// on the host. Nothing on an execute path allocates, frees or synchronises.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdlib.h>
+
+#include "host_common.hpp"
+#include "kernels.hpp"
+#include "twofold.h"
+
+using namespace twofold;
+using namespace twofold::host;
+
+namespace {
+
+// Tile table from device offsets (one block of 1024 threads), rows of 1024
+// segments: tiles per segment, block-wide exclusive scan, running carry.
+// Also records in *status whether the offsets are valid (offsets[0] >= 0,
+// non-decreasing, offsets[nseg] <= n_total).
+__global__ void __launch_bounds__(1024)
+seg_tiles_kernel(const int64_t* __restrict__ off, int64_t nseg, int64_t n_total, int64_t TS,
+                 int64_t* __restrict__ tbase, uint32_t* __restrict__ status) {
+  __shared__ int64_t sh[1024];
+  __shared__ int sh_bad;
+  const int t = threadIdx.x;
+  if (t == 0) sh_bad = (off[0] < 0 || off[nseg] > n_total) ? 1 : 0;
+  __syncthreads();
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nseg; base += 1024) {
+    const int64_t sg = base + t;
+    int64_t tiles = 0;
+    if (sg < nseg) {
+      const int64_t len = off[sg + 1] - off[sg];
+      if (len < 0) sh_bad = 1;  // benign race: every writer stores 1
+      tiles = len > 0 ? (len + TS - 1) / TS : 0;
+    }
+    sh[t] = tiles;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+      const int64_t v = t >= d ? sh[t - d] : 0;
+      __syncthreads();
+      sh[t] += v;
+      __syncthreads();
+    }
+    if (sg < nseg) tbase[sg] = carry + sh[t] - tiles;
+    carry += sh[1023];
+    __syncthreads();
+  }
+  if (t == 0) {
+    tbase[nseg] = carry;
+    *status = sh_bad ? 1u : 0u;
+  }
+}
+
+template <typename T, typename A, int M, bool DOT, bool YV>
+int launch_seg_u(const T* x, const T* y, const int64_t* off, int64_t nseg, const int64_t* tbase,
+                 const uint32_t* status, const twofold_launch_t& lc, double* slots, void* out,
+                 hipStream_t st) {
+  const dim3 grid(lc.grid_blocks), block(lc.block_threads);
+  const int64_t ts = lc.tile_elems;
+#define TWOFOLD_SEG(UU)                                                                       \
+  seg_kernel<T, A, M, DOT, YV, UU><<<grid, block, 0, st>>>(x, y, off, nseg, tbase, ts, status, \
+                                                           slots, out)
+  switch (lc.unroll) {
+    case 1: TWOFOLD_SEG(1); break;
+    case 2: TWOFOLD_SEG(2); break;
+    case 4: TWOFOLD_SEG(4); break;
+    default: TWOFOLD_SEG(8); break;
+  }
+#undef TWOFOLD_SEG
+  if (launch_status()) return TWOFOLD_EHIP;
+  const int64_t blocks2 = (nseg + 3) / 4;  // one wave per segment, 4 waves per block
+  seg_pass2_kernel<T, M><<<dim3(unsigned(blocks2)), dim3(256), 0, st>>>(tbase, nseg, status, slots,
+                                                                        out);
+  return launch_status();
+}
+
+template <typename T, typename A, int M, bool DOT>
+int launch_seg(const T* x, const T* y, const int64_t* off, int64_t nseg, const int64_t* tbase,
+               const uint32_t* status, const twofold_launch_t& lc, double* slots, void* out,
+               hipStream_t st) {
+  if constexpr (DOT) {
+    if (!y_vector_ok(x, y))
+      return launch_seg_u<T, A, M, DOT, false>(x, y, off, nseg, tbase, status, lc, slots, out, st);
+  }
+  return launch_seg_u<T, A, M, DOT, true>(x, y, off, nseg, tbase, status, lc, slots, out, st);
+}
+
+template <typename T, bool DOT>
+int seg_by_mode(int mode, const T* x, const T* y, const int64_t* off, int64_t nseg,
+                const int64_t* tbase, const uint32_t* status, const twofold_launch_t& lc,
+                double* slots, void* out, hipStream_t st) {
+#define TWOFOLD_SEG_MODE(A, MM) \
+  return launch_seg<T, A, MM, DOT>(x, y, off, nseg, tbase, status, lc, slots, out, st)
+  switch (mode) {
+    case kPlain: TWOFOLD_SEG_MODE(T, kPlain);
+    case kFast: TWOFOLD_SEG_MODE(T, kFast);
+    case kRigorous: TWOFOLD_SEG_MODE(T, kRigorous);
+    case kKahan: TWOFOLD_SEG_MODE(T, kKahan);
+    case kFastRounded:
+      if constexpr (DOT) TWOFOLD_SEG_MODE(T, kFastRounded);
+      return TWOFOLD_EINVAL;
+    case kRigorousRounded:
+      if constexpr (DOT) TWOFOLD_SEG_MODE(T, kRigorousRounded);
+      return TWOFOLD_EINVAL;
+    case kWide:
+      if constexpr (sizeof(T) == 4) TWOFOLD_SEG_MODE(double, kWide);
+      return TWOFOLD_EINVAL;
+    default: return TWOFOLD_EINVAL;
+  }
+#undef TWOFOLD_SEG_MODE
+}
+
+template <typename T, bool DOT>
+int seg_entry(const T* x, const T* y, int64_t n_total, const int64_t* off, int64_t nseg, int mode,
+              const twofold_launch_t* launch, void* out, void* ws, size_t ws_bytes, void* stream) {
+  const int dtype = int(sizeof(T));
+  if ((!x && n_total > 0) || !out || !off || (DOT && !y && n_total > 0) || n_total < 0 || nseg < 0)
+    return TWOFOLD_EINVAL;
+  // binary64 results (wide) go through a plan, whose output is untyped
+  if (!mode_ok(dtype, DOT, mode) || mode == kWide) return TWOFOLD_EINVAL;
+  if (!elem_aligned(x, dtype) || (DOT && !elem_aligned(y, dtype)) || !elem_aligned(out, dtype) ||
+      !elem_aligned(off, 8))
+    return TWOFOLD_EALIGN;
+  twofold_launch_t lc;
+  const int rc = resolve_seg(dtype, DOT, mode, n_total, launch, &lc);
+  if (rc) return rc;
+  if (nseg == 0) return TWOFOLD_OK;
+  const SegLayout L = seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems));
+  if (!ws_ok(ws, ws_bytes, L.total)) return TWOFOLD_EWORKSPACE;
+  char* base = static_cast<char*>(ws);
+  uint32_t* status = reinterpret_cast<uint32_t*>(base);
+  int64_t* tbase = reinterpret_cast<int64_t*>(base + L.tbase_off);
+  double* slots = reinterpret_cast<double*>(base + L.slots_off);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  seg_tiles_kernel<<<1, 1024, 0, st>>>(off, nseg, n_total, lc.tile_elems, tbase, status);
+  if (launch_status()) return TWOFOLD_EHIP;
+  return seg_by_mode<T, DOT>(mode, x, y, off, nseg, tbase, status, lc, slots, out, st);
+}
+
+}  // namespace
+
+// A plan owns the device copies of the offsets and of the tile table; the
+// caller's workspace holds the tile pairs.
+struct twofold_seg_plan {
+  int dtype, is_dot, mode;
+  int64_t nseg, ntiles, n_total;
+  twofold_launch_t lc;
+  int64_t* d_off;
+  int64_t* d_tbase;
+};
+
+extern "C" {
+
+size_t twofold_workspace_bytes_seg(int dtype, int is_dot, int mode, int64_t n_total, int64_t nseg,
+                                   const twofold_launch_t* launch) {
+  if (!valid_dtype(dtype) || n_total < 0 || nseg < 0 || !mode_ok(dtype, is_dot != 0, mode)) return 0;
+  twofold_launch_t lc;
+  if (resolve_seg(dtype, is_dot != 0, mode, n_total, launch, &lc)) return 0;
+  return seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems)).total;
+}
+
+int twofold_segsum_f32(const float* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
+                       int mode, const twofold_launch_t* launch, twofold_f32_t* out, void* ws,
+                       size_t ws_bytes, void* stream) {
+  return seg_entry<float, false>(x, nullptr, n_total, offsets, nseg, mode, launch, out, ws, ws_bytes,
+                                 stream);
+}
+int twofold_segsum_f64(const double* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
+                       int mode, const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                       size_t ws_bytes, void* stream) {
+  return seg_entry<double, false>(x, nullptr, n_total, offsets, nseg, mode, launch, out, ws, ws_bytes,
+                                  stream);
+}
+int twofold_segdot_f32(const float* x, const float* y, int64_t n_total, const int64_t* offsets,
+                       int64_t nseg, int mode, const twofold_launch_t* launch, twofold_f32_t* out,
+                       void* ws, size_t ws_bytes, void* stream) {
+  return seg_entry<float, true>(x, y, n_total, offsets, nseg, mode, launch, out, ws, ws_bytes, stream);
+}
+int twofold_segdot_f64(const double* x, const double* y, int64_t n_total, const int64_t* offsets,
+                       int64_t nseg, int mode, const twofold_launch_t* launch, twofold_f64_t* out,
+                       void* ws, size_t ws_bytes, void* stream) {
+  return seg_entry<double, true>(x, y, n_total, offsets, nseg, mode, launch, out, ws, ws_bytes, stream);
+}
+
+int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype, int is_dot,
+                            int mode, const twofold_launch_t* launch, twofold_seg_plan_t** plan) {
+  if (!plan) return TWOFOLD_EINVAL;
+  *plan = nullptr;
+  if (!offsets_host || nseg < 0 || !valid_dtype(dtype)) return TWOFOLD_EINVAL;
+  if (!mode_ok(dtype, is_dot != 0, mode)) return TWOFOLD_EINVAL;
+  if (offsets_host[0] != 0) return TWOFOLD_EOFFSETS;
+  for (int64_t s = 0; s < nseg; s++)
+    if (offsets_host[s + 1] < offsets_host[s]) return TWOFOLD_EOFFSETS;
+  const int64_t n_total = offsets_host[nseg];
+  twofold_launch_t lc;
+  const int rc = resolve_seg(dtype, is_dot != 0, mode, n_total, launch, &lc);
+  if (rc) return rc;
+  int64_t* tb = static_cast<int64_t*>(malloc(sizeof(int64_t) * size_t(nseg + 1)));
+  if (!tb) return TWOFOLD_EINVAL;
+  int64_t acc = 0;
+  for (int64_t s = 0; s < nseg; s++) {
+    tb[s] = acc;
+    const int64_t len = offsets_host[s + 1] - offsets_host[s];
+    acc += (len + lc.tile_elems - 1) / lc.tile_elems;
+  }
+  tb[nseg] = acc;
+  twofold_seg_plan* p = static_cast<twofold_seg_plan*>(calloc(1, sizeof(twofold_seg_plan)));
+  if (!p) {
+    free(tb);
+    return TWOFOLD_EINVAL;
+  }
+  p->dtype = dtype;
+  p->is_dot = is_dot != 0;
+  p->mode = mode;
+  p->nseg = nseg;
+  p->ntiles = acc;
+  p->n_total = n_total;
+  p->lc = lc;
+  const size_t bytes = sizeof(int64_t) * size_t(nseg + 1);
+  bool ok = hipMalloc(reinterpret_cast<void**>(&p->d_off), bytes) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&p->d_tbase), bytes) == hipSuccess &&
+            hipMemcpy(p->d_off, offsets_host, bytes, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(p->d_tbase, tb, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  free(tb);
+  if (!ok) {
+    if (p->d_off) (void)hipFree(p->d_off);
+    if (p->d_tbase) (void)hipFree(p->d_tbase);
+    free(p);
+    return TWOFOLD_EHIP;
+  }
+  *plan = p;
+  return TWOFOLD_OK;
+}
+
+size_t twofold_seg_plan_workspace_bytes(const twofold_seg_plan_t* plan) {
+  if (!plan) return 0;
+  return align256(size_t(16) * size_t(plan->ntiles > 0 ? plan->ntiles : 1));
+}
+
+int twofold_seg_plan_get_launch(const twofold_seg_plan_t* plan, twofold_launch_t* out) {
+  if (!plan || !out) return TWOFOLD_EINVAL;
+  *out = plan->lc;
+  return TWOFOLD_OK;
+}
+
+int twofold_seg_plan_execute(const twofold_seg_plan_t* plan, const void* x, const void* y,
+                             void* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !out) return TWOFOLD_EINVAL;
+  if (plan->n_total > 0 && (!x || (plan->is_dot && !y))) return TWOFOLD_EINVAL;
+  if (!plan->is_dot && y) return TWOFOLD_EINVAL;
+  const int dtype = plan->dtype;
+  if (!elem_aligned(x, dtype) || (y && !elem_aligned(y, dtype)) ||
+      !elem_aligned(out, out_f64(dtype, plan->mode) ? 8 : 4))
+    return TWOFOLD_EALIGN;
+  if (plan->nseg == 0) return TWOFOLD_OK;
+  if (!ws_ok(ws, ws_bytes, twofold_seg_plan_workspace_bytes(plan))) return TWOFOLD_EWORKSPACE;
+  double* slots = static_cast<double*>(ws);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t* off = plan->d_off;
+  const int64_t* tb = plan->d_tbase;
+  const int64_t ns = plan->nseg;
+  const twofold_launch_t& lc = plan->lc;
+  if (dtype == 4) {
+    const float* xf = static_cast<const float*>(x);
+    const float* yf = static_cast<const float*>(y);
+    if (plan->is_dot)
+      return seg_by_mode<float, true>(plan->mode, xf, yf, off, ns, tb, nullptr, lc, slots, out, st);
+    return seg_by_mode<float, false>(plan->mode, xf, yf, off, ns, tb, nullptr, lc, slots, out, st);
+  }
+  const double* xd = static_cast<const double*>(x);
+  const double* yd = static_cast<const double*>(y);
+  if (plan->is_dot)
+    return seg_by_mode<double, true>(plan->mode, xd, yd, off, ns, tb, nullptr, lc, slots, out, st);
+  return seg_by_mode<double, false>(plan->mode, xd, yd, off, ns, tb, nullptr, lc, slots, out, st);
+}
+
+int twofold_seg_plan_destroy(twofold_seg_plan_t* plan) {
+  if (!plan) return TWOFOLD_OK;
+  int rc = TWOFOLD_OK;
+  if (plan->d_off && hipFree(plan->d_off) != hipSuccess) rc = TWOFOLD_EHIP;
+  if (plan->d_tbase && hipFree(plan->d_tbase) != hipSuccess) rc = TWOFOLD_EHIP;
+  free(plan);
+  return rc;
+}
+
+}  // extern "C"

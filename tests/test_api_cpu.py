@@ -72,6 +72,11 @@ def test_single_argument_checks():
     assert L.twofold_sum_f32(fake, 10, 7, None, fake, ws, big, None) == EINVAL
     assert L.twofold_sum_f32(fake, 10, 3, None, fake, ws, big, None) == EINVAL  # wide: use sumd
     assert L.twofold_sum_f64(fake, 10, 3, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_sum_f32(fake, 10, 5, None, fake, ws, big, None) == EINVAL  # rounded: dots only
+    assert L.twofold_sum_f64(fake, 10, 6, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_sum_f64(fake, 10, 8, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_workspace_bytes_single(4, 0, 5, 100, None) == 0
+    assert L.twofold_workspace_bytes_single(4, 1, 5, 100, None) > 0
     assert L.twofold_dot_f64(fake, None, 10, 2, None, fake, ws, big, None) == EINVAL
     # misaligned data
     assert L.twofold_sum_f64(ctypes.c_void_p(0x10004), 10, 2, None, fake, ws, big, None) == EALIGN

@@ -27,8 +27,9 @@ def _rows(t):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-@pytest.mark.parametrize("is_dot", [False, True])
-@pytest.mark.parametrize("mode", ["plain", "fast", "rigorous"])
+@pytest.mark.parametrize("is_dot,mode", [(d, m) for d in (False, True)
+                                         for m in ("plain", "fast", "rigorous", "kahan")]
+                         + [(True, "fast_rounded"), (True, "rigorous_rounded")])
 def test_seg_bitwise_vs_model(dtype, is_dot, mode):
     W = 16 // np.dtype(dtype).itemsize
     L = _lengths()

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 SIZES = [0, 1, 3, 17, 1000, 4097, 65536 + 5, (1 << 20) + 3]
 LAUNCHES = [(256, 1, 1), (256, 4, 7), (512, 2, 3), (1024, 8, 5), (256, 4, 300), (64, 2, 2),
             (128, 8, 33)]
-MODES = ["plain", "fast", "rigorous"]
+MODES = ["plain", "fast", "rigorous", "kahan"]
 SHIFTS = [(0, 0), (1, 0), (3, 1), (2, 2)]
 
 
@@ -47,6 +47,20 @@ def test_bitwise_vs_model(dtype, is_dot, mode):
                 got = pair(tf.dot(xd, yd, mode, lc) if is_dot else tf.sum(xd, mode, lc))
                 want = oracle.model_single(mode, x, y if is_dot else None, mis, bt, u, gb)
                 assert same_bits(got, want), (n, bt, u, gb, xs, ys, got, list(want))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("mode", ["fast_rounded", "rigorous_rounded"])
+def test_rounded_product_dots_vs_model(dtype, mode):
+    for n in SIZES:
+        x, y = _data(n + 3, n, dtype)
+        for li, (bt, u, gb) in enumerate(LAUNCHES):
+            xs, ys = SHIFTS[li % len(SHIFTS)]
+            xd, mis = to_dev(x, xs)
+            yd, _ = to_dev(y, ys)
+            got = pair(tf.dot(xd, yd, mode, launch(bt, u, gb)))
+            want = oracle.model_single(mode, x, y, mis, bt, u, gb)
+            assert same_bits(got, want), (n, bt, u, gb, xs, ys)
 
 
 @pytest.mark.parametrize("is_dot", [False, True])
@@ -174,6 +188,43 @@ def test_workspace_needs_no_preparation():
     none.ptr, none.nbytes = 0, 0
     v, e = pair(tf.sum(xd, "rigorous", launch(256, 2, 1), ws=none))
     assert ex.diff(v, e) == 0.0
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_subnormals_kept(dtype):
+    """Subnormal data and subnormal FMA remainders: a flush-to-zero build
+    would lose them. Compared bitwise with the order model (IEEE, no
+    flushing) and, for the sums, exactly with the exact accumulator."""
+    fi = np.finfo(dtype)
+    rng = np.random.default_rng(17)
+    n = 70001
+    # sums: values spread over the subnormal and lowest normal binades
+    e = rng.integers(fi.minexp - fi.nmant, fi.minexp + 3, n)
+    x = np.ldexp(rng.uniform(-1, 1, n), e).astype(dtype)
+    assert np.count_nonzero(np.abs(x) < fi.tiny) > n // 4
+    xd, mis = to_dev(x, 1)
+    for mode in ("fast", "rigorous"):
+        got = pair(tf.sum(xd, mode, launch(256, 4, 9)))
+        assert same_bits(got, oracle.model_single(mode, x, None, mis, 256, 4, 9)), mode
+        # every round-off here is a multiple of 2^-149 small enough to be
+        # held exactly, so the rigorous value + error is the exact sum (the
+        # fast form can lose: t - s needs up to 26 bits on this data)
+        if mode == "rigorous":
+            assert oracle.Exact(x).diff(*got) == 0.0
+    # dots: products near the bottom of the normal range, so their remainders
+    # are subnormal
+    a = np.ldexp(rng.uniform(1, 2, n), rng.integers(fi.minexp // 2 - 2, fi.minexp // 2 + 2, n))
+    b = np.ldexp(rng.uniform(-2, 2, n), rng.integers(fi.minexp // 2 - 2, fi.minexp // 2 + 2, n))
+    a, b = a.astype(dtype), b.astype(dtype)
+    p = a * b
+    rem = np.abs(p.astype(np.float64) - (a.astype(np.float64) * b.astype(np.float64)))
+    if dtype == np.float32:
+        assert np.count_nonzero((rem > 0) & (rem < float(fi.tiny))) > n // 10
+    ad, mis = to_dev(a, 2)
+    bd, _ = to_dev(b, 1)
+    for mode in ("fast", "rigorous", "plain"):
+        got = pair(tf.dot(ad, bd, mode, launch(512, 2, 5)))
+        assert same_bits(got, oracle.model_single(mode, a, b, mis, 512, 2, 5)), mode
 
 
 def test_hundred_hours_on_gpu():

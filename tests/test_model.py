@@ -25,17 +25,18 @@ def _u(dtype):
     return 2.0 ** -(np.finfo(dtype).nmant + 1)
 
 
+SEQ = {("plain", False): "sum", ("plain", True): "dot", ("fast", False): "sumtf",
+       ("fast", True): "dottf", ("rigorous", False): "sumt", ("rigorous", True): "dott",
+       ("kahan", False): "sumk_pair", ("kahan", True): "dotk_pair",
+       ("fast_rounded", True): "dottf_rounded", ("rigorous_rounded", True): "dott_rounded"}
+
+
 def _seq_kind(mode, is_dot):
-    if mode == "plain":
-        return "dot" if is_dot else "sum"
-    if mode == "fast":
-        return "dottf" if is_dot else "sumtf"
-    return "dott" if is_dot else "sumt"
+    return SEQ[(mode, is_dot)]
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-@pytest.mark.parametrize("mode", ["plain", "fast", "rigorous"])
-@pytest.mark.parametrize("is_dot", [False, True])
+@pytest.mark.parametrize("mode,is_dot", [(m, d) for (m, d) in SEQ])
 def test_single_lane_reduces_to_sequential(dtype, mode, is_dot):
     W = 16 // np.dtype(dtype).itemsize
     bt, U, gb = 256, 2, 3
@@ -193,12 +194,33 @@ def test_segmented_exact_grid_and_bound(dtype):
         assert abs(ex.diff(*gotd[s])) <= 4 * (b - a) * u * u * ex.A
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_kahan_and_rounded_forms(dtype):
+    """Kahan's value is compensated: within the classical (2u + O(n u^2))
+    sum|x| of the exact sum, far better than the plain value; its error is
+    the pending correction. The rounded-product dots share the FMA dots'
+    value but miss the products' rounding."""
+    u = _u(dtype)
+    x, y = synth.uniform(44, 1 << 15, dtype, count=2)
+    ex = oracle.Exact(x)
+    k = oracle.model_single("kahan", x, None, 1, 256, 2, 3)
+    assert abs(ex.diff(k[0])) <= 2 * u * ex.A + 4 * x.size * u * u * ex.A
+    assert abs(ex.diff(k[0], k[1])) <= abs(ex.diff(k[0]))
+    exd = oracle.Exact(x, y)
+    fr = oracle.model_single("rigorous_rounded", x, y, 0, 256, 2, 3)
+    fm = oracle.model_single("rigorous", x, y, 0, 256, 2, 3)
+    assert fr[0] == fm[0]
+    assert abs(exd.diff(*fr)) > 10 * abs(exd.diff(*fm))
+
+
 def test_model_rejects_bad_arguments():
     x = np.zeros(10)
     with pytest.raises(ValueError):
         oracle.model_single("rigorous", x, None, 0, 100, 1, 1)
     with pytest.raises(ValueError):
         oracle.model_single("wide", x, None, 0, 256, 1, 1)
+    with pytest.raises(ValueError):
+        oracle.model_single("fast_rounded", x, None, 0, 256, 1, 1)
     with pytest.raises(ValueError):
         oracle.model_seg("rigorous", x, [0, 5, 3], None, 0, 1, 128)
     with pytest.raises(ValueError):
