@@ -60,12 +60,43 @@ def gpu_results(dev_in, tf):
     return res
 
 
+def host_info():
+    """CPU model string and the cores this process may run on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu": model, "cores_available": avail}
+
+
+def exact_timing(oracle, x, y):
+    """Gelem/s of the oracle's exact accumulator on one pair, on one thread
+    and on every thread it uses by default."""
+    res = {}
+    for label, nt in (("1_thread", 1), ("all_threads", oracle.default_threads())):
+        t0 = time.perf_counter()
+        oracle.Exact(x, y, nthreads=nt)
+        res[label] = {"threads": nt, "gelem_s": round(x.size / (time.perf_counter() - t0) / 1e9, 4)}
+    return res
+
+
 def oracle_leg(host, gpu):
     """The CPU-baseline leg, the only part of the benchmark that runs the
     oracle: (1) times the oracle's sequential rigorous and fast twofold dots
     (paper order, FMA remainder) over every input of one step on one host
-    thread; (2) grades the GPU's pairs against the exact accumulator:
-    |v + e - S| / sum|x y|, median over the conditions."""
+    thread, and its exact accumulator on one pair; (2) grades the GPU's pairs
+    against the exact accumulator: |v + e - S| / sum|x y| and |v - S| /
+    sum|x y|, median over the conditions, and the estimate quality
+    q = e / (S - v)."""
     import numpy as np
 
     import oracle
@@ -79,7 +110,10 @@ def oracle_leg(host, gpu):
     dt_s = time.perf_counter() - t0
     base = {"value": round(elems / dt_s / 1e9, 4), "unit": "Gelem/s", "cores": 1, "kind": "oracle",
             "sample": "one full step: sequential rigorous + fast twofold dot (paper order, FMA "
-                      "remainder) over the 12 ill-conditioned pairs, N=2^24 each, %.1f s" % dt_s}
+                      "remainder) over the 12 ill-conditioned pairs, N=2^24 each, %.1f s" % dt_s,
+            "host": host_info(),
+            "exact_accumulator": dict(sample="binary64 pair of target cond 1e16, N=2^24",
+                                      **exact_timing(oracle, *host[(np.float64, 16)]))}
     rows = {}
     for (dt, d), (x, y) in host.items():
         ex = oracle.Exact(x, y)
@@ -87,22 +121,88 @@ def oracle_leg(host, gpu):
         for mode in ("plain", "fast", "rigorous"):
             p = gpu[(dt, d, mode)]
             rows.setdefault("%s_%s" % (key, mode), []).append(abs(ex.diff(p[0], p[1])) / ex.A)
+            if mode != "plain":
+                dv = ex.diff(p[0])  # v - S, rounded once
+                rows.setdefault("%s_%s_value" % (key, mode), []).append(abs(dv) / ex.A)
+                rows.setdefault("%s_%s_q" % (key, mode), []).append(
+                    p[1] / -dv if dv else float("nan"))
         if dt == np.float32:
             p = gpu[(dt, d, "dotd")]
             rows.setdefault("f32data_f64plain", []).append(abs(ex.diff(p[0])) / ex.A)
         rows.setdefault("cond_" + key, []).append(2 * ex.A / abs(ex.S) if ex.S else float("inf"))
-    acc = {"measure": "median over conditions of |v + e - S| / sum|x y|"}
+    acc = {"measure": "median over conditions of |v + e - S| / sum|x y| (*_value: |v - S| / "
+                      "sum|x y|; *_q: e / (S - v))"}
     for k, v in rows.items():
         acc[k] = ["%.3g" % c for c in v] if k.startswith("cond_") else float("%.3g" % np.median(v))
     return base, acc
+
+
+def precision_study(torch, tf, dev, with_oracle):
+    """The binary32 precision form: N = 2^26 binary32 pairs x = m 2^k, y
+    likewise (m uniform(-1, 1), k uniform integer in [-20, 20], seed 2).
+    Times the binary32 plain, fast and rigorous twofold dots, the binary64
+    plain dot of the same binary32 data (dotd) and the binary64 plain and
+    rigorous dots over a binary64 copy (twice the bytes), HIP-graph replay.
+    Its CPU-baseline leg grades every result against the exact accumulator
+    and times the oracle's sequential rigorous dot on the same data. One
+    JSON line."""
+    import numpy as np
+    import synth
+
+    n = 1 << 26
+    log("precision study: generating N=2^26 scaled binary32 pairs")
+    x, y = synth.scaled(2, n)
+    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    x64, y64 = xd.double(), yd.double()
+    L = tf._lib.load()
+    ws = tf.Workspace(max(L.twofold_workspace_bytes_single(sz, 1, m, n, None)
+                          for sz, m in ((4, 0), (4, 1), (4, 2), (4, 3), (8, 0), (8, 2))), dev)
+    forms = [("f32 plain", lambda o: tf.dot(xd, yd, "plain", out=o, ws=ws), 4),
+             ("f32 fast twofold", lambda o: tf.dot(xd, yd, "fast", out=o, ws=ws), 4),
+             ("f32 rigorous twofold", lambda o: tf.dot(xd, yd, "rigorous", out=o, ws=ws), 4),
+             ("f64 plain on f32 data (dotd)", lambda o: tf.dotd(xd, yd, out=o, ws=ws), 8),
+             ("f64 plain on an f64 copy", lambda o: tf.dot(x64, y64, "plain", out=o, ws=ws), 8),
+             ("f64 rigorous on an f64 copy", lambda o: tf.dot(x64, y64, "rigorous", out=o, ws=ws),
+              8)]
+    rows, results = [], {}
+    for name, fn, osz in forms:
+        o = torch.empty(2, dtype=torch.float64, device=dev)
+        ov = o if osz == 8 else o.view(torch.float32)[:2]
+        t, tmin = graph_time(torch, lambda: (fn(ov), 1)[1])
+        results[name] = ov.double().cpu().numpy()
+        nbytes = 2 * n * (4 if "f32 data" in name or name.startswith("f32") else 8)
+        rows.append({"form": name, "us": round(t * 1e6, 2), "us_min": round(tmin * 1e6, 2),
+                     "gelem_s": round(n / t / 1e9, 1), "gb_s": round(nbytes / t / 1e9, 1),
+                     "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4)})
+        log("  %-30s %8.2f us %7.1f Gelem/s" % (name, t * 1e6, n / t / 1e9))
+    res = {"workload": "precision form: binary32 twofold vs binary64 plain, N=2^26, "
+                       "x, y = uniform(-1,1) * 2^k, k in [-20, 20], seed 2",
+           "n": n, "rows": rows}
+    if with_oracle:
+        import oracle
+        log("precision study: cpu baseline leg (exact grading, sequential oracle timing)")
+        ex = oracle.Exact(x, y)
+        for r in rows:
+            v, e = results[r["form"]]
+            r["err_rel"] = float("%.3g" % (abs(ex.diff(v, e)) / ex.A))
+        t0 = time.perf_counter()
+        oracle.seq("dott", x, y)
+        dt_s = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(n / dt_s / 1e9, 4), "unit": "Gelem/s", "cores": 1,
+                               "kind": "oracle", "sample": "sequential rigorous twofold dot "
+                               "(paper order, FMA remainder) of the whole pair, %.1f s" % dt_s,
+                               "host": host_info()}
+        res["err_measure"] = "|v + e - S| / sum|x y| against the exact accumulator"
+    print(json.dumps(res), flush=True)
 
 
 COPY_BYTES = 1 << 28
 FORMS = ("plain", "fast", "rigorous")
 
 
-def graph_time(torch, calls, reps=5):
-    """Median seconds per call over `reps` replays of a graph of calls()."""
+def graph_time(torch, calls, reps=30):
+    """(median, min) seconds per call over `reps` replays of a graph of
+    calls()."""
     import statistics
     calls()
     torch.cuda.synchronize()
@@ -122,6 +222,29 @@ def graph_time(torch, calls, reps=5):
         e1.record(st)
         e1.synchronize()
         ts.append(e0.elapsed_time(e1) * 1e-3 / ncalls)
+    return statistics.median(ts), min(ts)
+
+
+SCRUB_BYTES = 1 << 29
+
+
+def cold_time(torch, call, scrub, reps=30):
+    """Median seconds of one call whose inputs were evicted from every cache
+    level: each rep first reads and writes a 512 MiB scrub buffer (longer
+    than the host needs to enqueue the call, so the events around the call
+    time it back to back on the device)."""
+    import statistics
+    st = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        scrub.add_(1.0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        call()
+        e1.record(st)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
     return statistics.median(ts)
 
 
@@ -145,6 +268,7 @@ def roofline_sweep(torch, tf, dev):
     import synth
 
     rows = []
+    scrub = torch.zeros(SCRUB_BYTES // 4, dtype=torch.float32, device=dev)
     for dtype, tdt in ((np.float32, torch.float32), (np.float64, torch.float64)):
         size = np.dtype(dtype).itemsize
         for n in (4096, 1 << 20, (1 << 30) // size):
@@ -152,7 +276,8 @@ def roofline_sweep(torch, tf, dev):
             rng_chunks = synth.uniform_chunks(1, 2 * n, dtype)
             both = to_device_chunks(torch, rng_chunks, 2 * n, tdt, dev)
             x, y = both[:n], both[n:]  # x drawn entirely, then y
-            reps = 1 if n * size >= (1 << 28) else 50
+            big = n * size >= (1 << 28)
+            reps = 4 if big else 50  # calls per graph: amortizes the replay's own start
             for op in ("sum", "dot"):
                 forms = FORMS + ("kahan",) + (("wide",) if dtype == np.float32 else ())
                 if op == "dot":
@@ -164,27 +289,38 @@ def roofline_sweep(torch, tf, dev):
                         size, op == "dot", tf.mode_id(form), n, None)
                     ws = tf.Workspace(need, dev)
 
+                    def one():
+                        if form == "wide":
+                            (tf.dotd(x, y, out=o, ws=ws) if op == "dot"
+                             else tf.sumd(x, out=o, ws=ws))
+                        elif op == "dot":
+                            tf.dot(x, y, form, out=o, ws=ws)
+                        else:
+                            tf.sum(x, form, out=o, ws=ws)
+
                     def calls():
                         for _ in range(reps):
-                            if form == "wide":
-                                (tf.dotd(x, y, out=o, ws=ws) if op == "dot"
-                                 else tf.sumd(x, out=o, ws=ws))
-                            elif op == "dot":
-                                tf.dot(x, y, form, out=o, ws=ws)
-                            else:
-                                tf.sum(x, form, out=o, ws=ws)
+                            one()
                         return reps
 
-                    t = graph_time(torch, calls)
+                    t, tmin = graph_time(torch, calls)
+                    first = o.clone()
                     nbytes = n * size * (2 if op == "dot" else 1)
-                    rows.append({"dtype": np.dtype(dtype).name, "op": op, "form": form, "n": n,
-                                 "us": round(t * 1e6, 3), "gelem_s": round(n / t / 1e9, 2),
-                                 "gb_s": round(nbytes / t / 1e9, 1),
-                                 "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4)})
-                    log("  %s %-8s %8.2f us %8.1f GB/s" % (op, form, t * 1e6, nbytes / t / 1e9))
+                    row = {"dtype": np.dtype(dtype).name, "op": op, "form": form, "n": n,
+                           "us": round(t * 1e6, 3), "us_min": round(tmin * 1e6, 3),
+                           "gelem_s": round(n / t / 1e9, 2), "gb_s": round(nbytes / t / 1e9, 1),
+                           "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4)}
+                    if not big:
+                        row["us_cold"] = round(cold_time(torch, one, scrub) * 1e6, 3)
+                    row["bitwise_repeatable"] = bool(torch.equal(first.view(torch.int8),
+                                                                 o.view(torch.int8)))
+                    rows.append(row)
+                    log("  %s %-16s %10.2f us %8.1f GB/s" % (op, form, t * 1e6, nbytes / t / 1e9))
             del both, x, y
             torch.cuda.empty_cache()
-    print(json.dumps({"workload": "roofline sweep, uniform(-1,1) seed 1, tuned default launches",
+    print(json.dumps({"workload": "roofline sweep, uniform(-1,1) seed 1, tuned default launches; "
+                                  "us = median over 30 graph replays of 50 calls (4 at 1 GiB) "
+                                  "per call, warm; us_cold = one call after a 512 MiB scrub",
                       "peak_gb_s": HBM_PEAK_GBS, "rows": rows}), flush=True)
 
 
@@ -208,10 +344,14 @@ def segmented_batch(torch, tf, dev):
             plan = tf.SegPlan(off, tdt, True, form)
             out = torch.empty((plan.nseg, 2), dtype=plan.out_dtype, device=dev)
             ws = tf.Workspace(plan.workspace_bytes, dev)
-            t = graph_time(torch, lambda: (plan.execute(x, y, out=out, ws=ws), 1)[1])
+            t, tmin = graph_time(torch, lambda: (plan.execute(x, y, out=out, ws=ws), 1)[1], reps=10)
+            first = out.clone()
+            plan.execute(x, y, out=out, ws=ws)
+            same = bool(torch.equal(first.view(torch.int8), out.view(torch.int8)))
             nbytes = 2 * n * np.dtype(dtype).itemsize
             rows.append({"dtype": np.dtype(dtype).name, "form": form, "nseg": int(plan.nseg),
-                         "elements": n, "ms": round(t * 1e3, 4), "gelem_s": round(n / t / 1e9, 1),
+                         "elements": n, "ms": round(t * 1e3, 4), "ms_min": round(tmin * 1e3, 4),
+                         "bitwise_repeatable": same, "gelem_s": round(n / t / 1e9, 1),
                          "gb_s": round(nbytes / t / 1e9, 1),
                          "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
                          "launch": plan.launch.as_dict()})
@@ -270,10 +410,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--workload", choices=("illcond", "sweep", "segmented"), default="illcond",
+    ap.add_argument("--workload", choices=("illcond", "sweep", "segmented", "precision"),
+                    default="illcond",
                     help="illcond: the headline line (default); sweep: the roofline sweep of "
                          "every form at 4096, 2^20 and 1 GiB per vector; segmented: the "
-                         "20,000-segment batch")
+                         "20,000-segment batch; precision: binary32 twofold against binary64 "
+                         "plain at N=2^26")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library's reduction runs on one device "
@@ -294,6 +436,9 @@ def main():
         return
     if args.workload == "segmented":
         segmented_batch(torch, tf, dev)
+        return
+    if args.workload == "precision":
+        precision_study(torch, tf, dev, not args.no_cpu_baseline)
         return
     log("generating 12 ill-conditioned pairs, N=2^24")
     t0 = time.perf_counter()
@@ -332,6 +477,7 @@ def main():
     calls(f64 + f32, "rigorous")  # eager run first: loads the library, checks the calls
     calls(f64 + f32, "fast")
     torch.cuda.synchronize()
+    eager = {k: v.clone() for k, v in outs.items()}
     gA, gB = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
     with torch.cuda.graph(gA, stream=cap):
         calls(f64, "rigorous")
@@ -378,6 +524,8 @@ def main():
     bytes_launch = 2 * N * 8  # x and y, binary64
     achieved = bytes_launch / avg / 1e9
     lc = tf.default_launch(0, 8, True, "rigorous", N)
+    # every pair of the last timed step against the eager run, bit for bit
+    repeatable = all(torch.equal(eager[k].view(torch.int8), outs[k].view(torch.int8)) for k in outs)
     log("step %.3f ms, %.1f Gelem/s; f64 rigorous dot %.1f us avg, %.0f GB/s"
         % (ms_step, value, avg * 1e6, achieved))
 
@@ -390,6 +538,7 @@ def main():
                                "N=2^24, target cond 1e6..1e16 (12 pairs, 24 dots per step, "
                                "HIP-graph replay)",
                    "n": N, "pairs": len(dev_in), "dots_per_step": ndots},
+        "bitwise_repeatable": repeatable,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
