@@ -234,34 +234,63 @@ single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restric
 }
 
 // ---- segmented ---------------------------------------------------------------
-// Pass 1: persistent waves over a tile list. tbase[s] = number of tiles of
-// the segments before s (tbase[nseg] = total NT). Wave w takes tiles
-// [floor(w*NT/NW), floor((w+1)*NT/NW)). A one-tile segment is finalized
-// here; the pair of a tile of a longer segment goes to slots[tile].
+// Which wave takes which tile does not change any result; the assignment
+// balances bytes. A tile costs its length plus c0 = 64*W*U elements (one
+// round of its wave, standing for the tile's start-up), so the tiles before
+// segment s cost cbase(s) = (off[s] - off[0]) + c0*tbase[s], and the total
+// is C = cbase(nseg). Wave w of NW takes the tiles whose start cost lies in
+// [floor(w*C/NW), floor((w+1)*C/NW)).
+__device__ __forceinline__ int64_t seg_cost_bound(int64_t w, int64_t C, int64_t NW) {
+  return static_cast<int64_t>((static_cast<__int128>(w) * C) / NW);
+}
+
+// Pass 1: persistent waves over the tile list. tbase[s] = number of tiles
+// of the segments before s (tbase[nseg] = total NT). With a wave table
+// (plans), wave w reads its first tile, that tile's segment and its end
+// from wtab[2w], wtab[2w+1], wtab[2w+2]; without one it finds them by two
+// interleaved binary searches over the segments' costs. A one-tile segment
+// is finalized here; the pair of a tile of a longer segment goes to
+// slots[tile].
 template <typename T, typename A, int M, bool DOT, bool YV, int U>
 __global__ void __launch_bounds__(1024)
 seg_kernel(const T* __restrict__ x, const T* __restrict__ y, const int64_t* __restrict__ off,
-           int64_t nseg, const int64_t* __restrict__ tbase, int64_t TS,
-           const uint32_t* __restrict__ status, double* __restrict__ slots,
+           int64_t nseg, const int64_t* __restrict__ tbase, const int64_t* __restrict__ wtab,
+           int64_t TS, const uint32_t* __restrict__ status, double* __restrict__ slots,
            void* __restrict__ out) {
   if (status && *status != 0) return;  // invalid offsets: pass 2 reports NaN
   const int lane = threadIdx.x & 63;
   const int64_t wpb = blockDim.x >> 6;
   const int64_t w = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6);
-  const int64_t NW = static_cast<int64_t>(gridDim.x) * wpb;
-  const int64_t NT = tbase[nseg];
-  const int64_t t0 = (w * NT) / NW, t1 = ((w + 1) * NT) / NW;
-  if (t0 >= t1) return;
-  // Segment of tile t0: tbase[lo] <= t0 < tbase[lo + 1].
-  int64_t lo = 0, hi = nseg;
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (tbase[mid] <= t0)
-      lo = mid;
-    else
-      hi = mid;
+  int64_t t0, t1, sg;
+  if (wtab) {
+    t0 = wtab[2 * w];
+    sg = wtab[2 * w + 1];
+    t1 = wtab[2 * w + 2];
+  } else {
+    constexpr int64_t c0 = 64 * (16 / static_cast<int64_t>(sizeof(T))) * U;
+    const int64_t NW = static_cast<int64_t>(gridDim.x) * wpb;
+    const int64_t o0 = off[0];
+    const int64_t C = (off[nseg] - o0) + c0 * tbase[nseg];
+    const int64_t lo0 = seg_cost_bound(w, C, NW), lo1 = seg_cost_bound(w + 1, C, NW);
+    // Largest segment a with cbase(a) <= lo (cbase(0) = 0 <= lo), for both
+    // bounds at once.
+    int64_t a0 = 0, a1 = 0, n = nseg;
+    while (n > 1) {
+      const int64_t half = n >> 1;
+      const int64_t m0 = a0 + half, m1 = a1 + half;
+      if ((off[m0] - o0) + c0 * tbase[m0] <= lo0) a0 = m0;
+      if ((off[m1] - o0) + c0 * tbase[m1] <= lo1) a1 = m1;
+      n -= half;
+    }
+    // First tile at or after each bound: tile i of segment a starts at cost
+    // cbase(a) + i*(TS + c0); past the segment's last tile, the next
+    // segment's first tile.
+    const int64_t i0 = ((lo0 - (off[a0] - o0) - c0 * tbase[a0]) + TS + c0 - 1) / (TS + c0);
+    const int64_t i1 = ((lo1 - (off[a1] - o0) - c0 * tbase[a1]) + TS + c0 - 1) / (TS + c0);
+    t0 = (i0 < tbase[a0 + 1] - tbase[a0]) ? tbase[a0] + i0 : tbase[a0 + 1];
+    t1 = (i1 < tbase[a1 + 1] - tbase[a1]) ? tbase[a1] + i1 : tbase[a1 + 1];
+    sg = a0;
   }
-  int64_t sg = lo;
   for (int64_t t = t0; t < t1; t++) {
     while (tbase[sg + 1] <= t) sg++;
     const int64_t tb = tbase[sg];

@@ -59,13 +59,13 @@ seg_tiles_kernel(const int64_t* __restrict__ off, int64_t nseg, int64_t n_total,
 
 template <typename T, typename A, int M, bool DOT, bool YV>
 int launch_seg_u(const T* x, const T* y, const int64_t* off, int64_t nseg, const int64_t* tbase,
-                 const uint32_t* status, const twofold_launch_t& lc, double* slots, void* out,
-                 hipStream_t st) {
+                 const int64_t* wtab, const uint32_t* status, const twofold_launch_t& lc,
+                 double* slots, void* out, hipStream_t st) {
   const dim3 grid(lc.grid_blocks), block(lc.block_threads);
   const int64_t ts = lc.tile_elems;
 #define TWOFOLD_SEG(UU)                                                                       \
-  seg_kernel<T, A, M, DOT, YV, UU><<<grid, block, 0, st>>>(x, y, off, nseg, tbase, ts, status, \
-                                                           slots, out)
+  seg_kernel<T, A, M, DOT, YV, UU><<<grid, block, 0, st>>>(x, y, off, nseg, tbase, wtab, ts, \
+                                                           status, slots, out)
   switch (lc.unroll) {
     case 1: TWOFOLD_SEG(1); break;
     case 2: TWOFOLD_SEG(2); break;
@@ -82,21 +82,23 @@ int launch_seg_u(const T* x, const T* y, const int64_t* off, int64_t nseg, const
 
 template <typename T, typename A, int M, bool DOT>
 int launch_seg(const T* x, const T* y, const int64_t* off, int64_t nseg, const int64_t* tbase,
-               const uint32_t* status, const twofold_launch_t& lc, double* slots, void* out,
-               hipStream_t st) {
+               const int64_t* wtab, const uint32_t* status, const twofold_launch_t& lc,
+               double* slots, void* out, hipStream_t st) {
   if constexpr (DOT) {
     if (!y_vector_ok(x, y))
-      return launch_seg_u<T, A, M, DOT, false>(x, y, off, nseg, tbase, status, lc, slots, out, st);
+      return launch_seg_u<T, A, M, DOT, false>(x, y, off, nseg, tbase, wtab, status, lc, slots,
+                                               out, st);
   }
-  return launch_seg_u<T, A, M, DOT, true>(x, y, off, nseg, tbase, status, lc, slots, out, st);
+  return launch_seg_u<T, A, M, DOT, true>(x, y, off, nseg, tbase, wtab, status, lc, slots, out,
+                                          st);
 }
 
 template <typename T, bool DOT>
 int seg_by_mode(int mode, const T* x, const T* y, const int64_t* off, int64_t nseg,
-                const int64_t* tbase, const uint32_t* status, const twofold_launch_t& lc,
-                double* slots, void* out, hipStream_t st) {
+                const int64_t* tbase, const int64_t* wtab, const uint32_t* status,
+                const twofold_launch_t& lc, double* slots, void* out, hipStream_t st) {
 #define TWOFOLD_SEG_MODE(A, MM) \
-  return launch_seg<T, A, MM, DOT>(x, y, off, nseg, tbase, status, lc, slots, out, st)
+  return launch_seg<T, A, MM, DOT>(x, y, off, nseg, tbase, wtab, status, lc, slots, out, st)
   switch (mode) {
     case kPlain: TWOFOLD_SEG_MODE(T, kPlain);
     case kFast: TWOFOLD_SEG_MODE(T, kFast);
@@ -140,19 +142,45 @@ int seg_entry(const T* x, const T* y, int64_t n_total, const int64_t* off, int64
   hipStream_t st = static_cast<hipStream_t>(stream);
   seg_tiles_kernel<<<1, 1024, 0, st>>>(off, nseg, n_total, lc.tile_elems, tbase, status);
   if (launch_status()) return TWOFOLD_EHIP;
-  return seg_by_mode<T, DOT>(mode, x, y, off, nseg, tbase, status, lc, slots, out, st);
+  return seg_by_mode<T, DOT>(mode, x, y, off, nseg, tbase, nullptr, status, lc, slots, out, st);
+}
+
+// Plans with at most this many waves carry a wave table (16 bytes a wave).
+constexpr int64_t kMaxPlanWaves = int64_t(1) << 20;
+
+// The wave table of a plan, from host offsets and tile table: for w = 0..NW,
+// wt[2w] = the first tile whose start cost is at least floor(w*C/NW) and
+// wt[2w+1] = the segment holding that tile (the last segment when the tile
+// index is NT). Same cost model as the kernel's own search: a tile costs its
+// length plus c0 = 64*W*U elements.
+void build_wave_table(const int64_t* off, const int64_t* tb, int64_t nseg, int64_t ts, int64_t c0,
+                      int64_t nw, int64_t* wt) {
+  const int64_t C = (off[nseg] - off[0]) + c0 * tb[nseg];
+  auto cbase = [&](int64_t s) { return (off[s] - off[0]) + c0 * tb[s]; };
+  int64_t a = 0, sg = 0;
+  for (int64_t w = 0; w <= nw; w++) {
+    const int64_t lo = static_cast<int64_t>((static_cast<__int128>(w) * C) / nw);
+    while (a + 1 < nseg && cbase(a + 1) <= lo) a++;
+    const int64_t i = ((lo - cbase(a)) + ts + c0 - 1) / (ts + c0);
+    const int64_t t = (i < tb[a + 1] - tb[a]) ? tb[a] + i : tb[a + 1];
+    if (sg < a) sg = a;
+    while (sg + 1 < nseg && tb[sg + 1] <= t) sg++;
+    wt[2 * w] = t;
+    wt[2 * w + 1] = sg;
+  }
 }
 
 }  // namespace
 
-// A plan owns the device copies of the offsets and of the tile table; the
-// caller's workspace holds the tile pairs.
+// A plan owns the device copies of the offsets, of the tile table and of
+// the wave table; the caller's workspace holds the tile pairs.
 struct twofold_seg_plan {
   int dtype, is_dot, mode;
   int64_t nseg, ntiles, n_total;
   twofold_launch_t lc;
   int64_t* d_off;
   int64_t* d_tbase;
+  int64_t* d_wtab;  // null above kMaxPlanWaves waves: the kernel searches
 };
 
 extern "C" {
@@ -223,14 +251,30 @@ int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype
   p->n_total = n_total;
   p->lc = lc;
   const size_t bytes = sizeof(int64_t) * size_t(nseg + 1);
-  bool ok = hipMalloc(reinterpret_cast<void**>(&p->d_off), bytes) == hipSuccess &&
-            hipMalloc(reinterpret_cast<void**>(&p->d_tbase), bytes) == hipSuccess &&
-            hipMemcpy(p->d_off, offsets_host, bytes, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(p->d_tbase, tb, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  const int64_t nw = int64_t(lc.grid_blocks) * (lc.block_threads / 64);
+  int64_t* wt = nullptr;
+  size_t wbytes = 0;
+  bool ok = true;
+  if (nseg > 0 && nw <= kMaxPlanWaves) {
+    wbytes = sizeof(int64_t) * size_t(2 * (nw + 1));
+    wt = static_cast<int64_t*>(malloc(wbytes));
+    ok = wt != nullptr;
+    if (ok) build_wave_table(offsets_host, tb, nseg, lc.tile_elems, 64 * (16 / dtype) * lc.unroll,
+                             nw, wt);
+  }
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&p->d_off), bytes) == hipSuccess &&
+       hipMalloc(reinterpret_cast<void**>(&p->d_tbase), bytes) == hipSuccess &&
+       hipMemcpy(p->d_off, offsets_host, bytes, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(p->d_tbase, tb, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && wt)
+    ok = hipMalloc(reinterpret_cast<void**>(&p->d_wtab), wbytes) == hipSuccess &&
+         hipMemcpy(p->d_wtab, wt, wbytes, hipMemcpyHostToDevice) == hipSuccess;
   free(tb);
+  free(wt);
   if (!ok) {
     if (p->d_off) (void)hipFree(p->d_off);
     if (p->d_tbase) (void)hipFree(p->d_tbase);
+    if (p->d_wtab) (void)hipFree(p->d_wtab);
     free(p);
     return TWOFOLD_EHIP;
   }
@@ -264,20 +308,25 @@ int twofold_seg_plan_execute(const twofold_seg_plan_t* plan, const void* x, cons
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t* off = plan->d_off;
   const int64_t* tb = plan->d_tbase;
+  const int64_t* wt = plan->d_wtab;
   const int64_t ns = plan->nseg;
   const twofold_launch_t& lc = plan->lc;
   if (dtype == 4) {
     const float* xf = static_cast<const float*>(x);
     const float* yf = static_cast<const float*>(y);
     if (plan->is_dot)
-      return seg_by_mode<float, true>(plan->mode, xf, yf, off, ns, tb, nullptr, lc, slots, out, st);
-    return seg_by_mode<float, false>(plan->mode, xf, yf, off, ns, tb, nullptr, lc, slots, out, st);
+      return seg_by_mode<float, true>(plan->mode, xf, yf, off, ns, tb, wt, nullptr, lc, slots, out,
+                                      st);
+    return seg_by_mode<float, false>(plan->mode, xf, yf, off, ns, tb, wt, nullptr, lc, slots, out,
+                                     st);
   }
   const double* xd = static_cast<const double*>(x);
   const double* yd = static_cast<const double*>(y);
   if (plan->is_dot)
-    return seg_by_mode<double, true>(plan->mode, xd, yd, off, ns, tb, nullptr, lc, slots, out, st);
-  return seg_by_mode<double, false>(plan->mode, xd, yd, off, ns, tb, nullptr, lc, slots, out, st);
+    return seg_by_mode<double, true>(plan->mode, xd, yd, off, ns, tb, wt, nullptr, lc, slots, out,
+                                     st);
+  return seg_by_mode<double, false>(plan->mode, xd, yd, off, ns, tb, wt, nullptr, lc, slots, out,
+                                    st);
 }
 
 int twofold_seg_plan_destroy(twofold_seg_plan_t* plan) {
@@ -285,6 +334,7 @@ int twofold_seg_plan_destroy(twofold_seg_plan_t* plan) {
   int rc = TWOFOLD_OK;
   if (plan->d_off && hipFree(plan->d_off) != hipSuccess) rc = TWOFOLD_EHIP;
   if (plan->d_tbase && hipFree(plan->d_tbase) != hipSuccess) rc = TWOFOLD_EHIP;
+  if (plan->d_wtab && hipFree(plan->d_wtab) != hipSuccess) rc = TWOFOLD_EHIP;
   free(plan);
   return rc;
 }

@@ -32,9 +32,14 @@ if ROOT not in sys.path:
 
 import paper_1401_0248_amd as tf  # noqa: E402
 
-MODES = {0: "plain", 1: "fast", 2: "rigorous", 3: "wide"}
-COMBOS = [(4, 0, 0), (4, 0, 1), (4, 0, 2), (4, 0, 3), (8, 0, 0), (8, 0, 1), (8, 0, 2),
-          (4, 1, 0), (4, 1, 1), (4, 1, 2), (4, 1, 3), (8, 1, 0), (8, 1, 1), (8, 1, 2)]
+MODES = {0: "plain", 1: "fast", 2: "rigorous", 3: "wide", 4: "kahan", 5: "fast_rounded",
+         6: "rigorous_rounded"}
+# (dtype, is_dot, mode): every form of the library; wide is binary32 only and
+# the rounded-product forms are dots only
+COMBOS = [(4, 0, 0), (4, 0, 1), (4, 0, 2), (4, 0, 3), (4, 0, 4),
+          (8, 0, 0), (8, 0, 1), (8, 0, 2), (8, 0, 4),
+          (4, 1, 0), (4, 1, 1), (4, 1, 2), (4, 1, 3), (4, 1, 4), (4, 1, 5), (4, 1, 6),
+          (8, 1, 0), (8, 1, 1), (8, 1, 2), (8, 1, 4), (8, 1, 5), (8, 1, 6)]
 INT64_MAX = "INT64_MAX"
 
 
@@ -42,7 +47,7 @@ def log(msg):
     print("[tune] " + msg, file=sys.stderr, flush=True)
 
 
-def time_graph(calls, reps=5):
+def time_graph(calls, reps=7):
     """Median seconds per call of a graph running calls() once."""
     s = torch.cuda.Stream()
     calls()  # eager once (checks the arguments, warms the caches of code)
@@ -141,7 +146,7 @@ def tune_seg(dev, quick):
             x = torch.empty(n, dtype=tdt, device=dev).uniform_(-1, 1)
             y = torch.empty(n, dtype=tdt, device=dev).uniform_(-1, 1) if is_dot else None
             best = None
-            cands = itertools.product((16, 32, 64) if quick else (8, 16, 32, 64, 128),
+            cands = itertools.product((16, 64) if quick else (16, 32, 64, 128, 256, 512),
                                       (2, 4) if quick else (2, 4, 8),
                                       (256, 512) if quick else (256, 512, 1024),
                                       (256, 1024) if quick else (256, 512, 1024))

@@ -30,11 +30,11 @@ pytestmark = pytest.mark.gpu
 
 N_ILL = 1 << 24
 # (dtype, is_dot, mode) -> (block_threads, unroll, max_blocks) for n <= 2^25
-BENCH_TABLE = {(8, 1, "rigorous"): (256, 2, 512), (8, 1, "fast"): (256, 2, 512),
+BENCH_TABLE = {(8, 1, "rigorous"): (512, 2, 256), (8, 1, "fast"): (256, 4, 256),
                (4, 1, "rigorous"): (256, 4, 256), (4, 1, "fast"): (256, 4, 256)}
 # segmented dots above 2^29 elements: (block_threads, unroll, grid, tile)
-SEG_TABLE = {(4, "rigorous"): (512, 4, 256, 8192), (4, "fast"): (256, 4, 512, 16384),
-             (8, "rigorous"): (256, 2, 512, 8192), (8, "fast"): (256, 2, 512, 8192)}
+SEG_TABLE = {(4, "rigorous"): (256, 2, 512, 16384), (4, "fast"): (256, 4, 512, 32768),
+             (8, "rigorous"): (256, 4, 256, 32768), (8, "fast"): (256, 4, 256, 32768)}
 
 
 def _u(dtype):
