@@ -89,17 +89,19 @@ def exact_timing(oracle, x, y):
     return res
 
 
-def oracle_leg(host, gpu):
+def oracle_leg(host, gpu, launches):
     """The CPU-baseline leg, the only part of the benchmark that runs the
     oracle: (1) times the oracle's sequential rigorous and fast twofold dots
     (paper order, FMA remainder) over every input of one step on one host
     thread, and its exact accumulator on one pair; (2) grades the GPU's pairs
     against the exact accumulator: |v + e - S| / sum|x y| and |v - S| /
-    sum|x y|, median over the conditions, and the estimate quality
-    q = e / (S - v)."""
+    sum|x y|, median over the conditions, the estimate quality
+    q = e / (S - v), and for the rigorous form the largest ratio of the
+    error to the proven bound of the launch's own tree."""
     import numpy as np
 
     import oracle
+    from oracle import bounds
 
     t0 = time.perf_counter()
     elems = 0
@@ -121,6 +123,12 @@ def oracle_leg(host, gpu):
         for mode in ("plain", "fast", "rigorous"):
             p = gpu[(dt, d, mode)]
             rows.setdefault("%s_%s" % (key, mode), []).append(abs(ex.diff(p[0], p[1])) / ex.A)
+            if mode == "rigorous":
+                lc = launches[(dt, mode)]
+                tb = bounds.single_bound(dt, x.size, lc.block_threads, lc.unroll, lc.grid_blocks,
+                                         ex.A)
+                rows.setdefault("%s_rigorous_over_tree_bound" % key, []).append(
+                    abs(ex.diff(p[0], p[1])) / tb)
             if mode != "plain":
                 dv = ex.diff(p[0])  # v - S, rounded once
                 rows.setdefault("%s_%s_value" % (key, mode), []).append(abs(dv) / ex.A)
@@ -131,9 +139,15 @@ def oracle_leg(host, gpu):
             rows.setdefault("f32data_f64plain", []).append(abs(ex.diff(p[0])) / ex.A)
         rows.setdefault("cond_" + key, []).append(2 * ex.A / abs(ex.S) if ex.S else float("inf"))
     acc = {"measure": "median over conditions of |v + e - S| / sum|x y| (*_value: |v - S| / "
-                      "sum|x y|; *_q: e / (S - v))"}
+                      "sum|x y|; *_q: e / (S - v); *_over_tree_bound: the largest |v + e - S| "
+                      "over the proven bound of the launch's reduction tree)"}
     for k, v in rows.items():
-        acc[k] = ["%.3g" % c for c in v] if k.startswith("cond_") else float("%.3g" % np.median(v))
+        if k.startswith("cond_"):
+            acc[k] = ["%.3g" % c for c in v]
+        elif k.endswith("_over_tree_bound"):
+            acc[k] = float("%.3g" % max(v))
+        else:
+            acc[k] = float("%.3g" % np.median(v))
     return base, acc
 
 
@@ -549,7 +563,9 @@ def main():
     if not args.no_cpu_baseline:
         gpu = gpu_results(dev_in, tf)
         log("cpu baseline leg: oracle timing and grading")
-        res["cpu_baseline"], res["accuracy"] = oracle_leg(host, gpu)
+        launches = {(dt, m): tf.default_launch(0, np.dtype(dt).itemsize, True, m, N)
+                    for dt in (np.float32, np.float64) for m in ("rigorous", "fast")}
+        res["cpu_baseline"], res["accuracy"] = oracle_leg(host, gpu, launches)
     print(json.dumps(res), flush=True)
 
 

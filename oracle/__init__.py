@@ -72,9 +72,9 @@ def lib():
         L.oracle_dotd_f32.restype = ctypes.c_double
         L.oracle_dotd_f32.argtypes = [vp, vp, i64]
         L.oracle_model_single.restype = i32
-        L.oracle_model_single.argtypes = [i32, i32, vp, vp, i64, i32, i32, i32, i32, vp]
+        L.oracle_model_single.argtypes = [i32, i32, vp, vp, i64, i32, i32, i32, i32, vp, vp]
         L.oracle_model_seg.restype = i32
-        L.oracle_model_seg.argtypes = [i32, i32, vp, vp, vp, i64, i32, i32, i64, vp]
+        L.oracle_model_seg.argtypes = [i32, i32, vp, vp, vp, i64, i32, i32, i64, vp, vp]
         _lib = L
     return _lib
 
@@ -167,26 +167,33 @@ def seq(kind, x, y=None):
     return out[0], out[1]
 
 
-def model_single(mode, x, y=None, x_misalign=0, block_threads=256, unroll=4, grid_blocks=1):
-    """(value, error) of the single-vector reduction in the GPU order."""
+def model_single(mode, x, y=None, x_misalign=0, block_threads=256, unroll=4, grid_blocks=1,
+                 with_violations=False):
+    """(value, error) of the single-vector reduction in the GPU order. With
+    with_violations, also the fast forms' sum of |item| over the steps that
+    break Theorem 1's condition (see ``fast_loss_bound``)."""
     x, y = _check(x, y)
     out = np.zeros(2, dtype=np.float64)
+    viol = np.zeros(1, dtype=np.float64)
     rc = lib().oracle_model_single(x.itemsize, MODES.get(mode, mode), _ptr(x), _ptr(y), x.size,
-                                   x_misalign, block_threads, unroll, grid_blocks, _ptr(out))
+                                   x_misalign, block_threads, unroll, grid_blocks, _ptr(out),
+                                   _ptr(viol))
     if rc != 0:
         raise ValueError("oracle_model_single rejected its arguments")
-    return out
+    return (out, float(viol[0])) if with_violations else out
 
 
-def model_seg(mode, x, offsets, y=None, x_misalign=0, unroll=4, tile_elems=4096):
+def model_seg(mode, x, offsets, y=None, x_misalign=0, unroll=4, tile_elems=4096,
+              with_violations=False):
     """(nseg, 2) array of (value, error) of the segmented reduction in the
-    GPU order."""
+    GPU order (and, with with_violations, the per-segment violation sums)."""
     x, y = _check(x, y)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     nseg = off.size - 1
     out = np.zeros((max(nseg, 0), 2), dtype=np.float64)
+    viol = np.zeros(max(nseg, 1), dtype=np.float64)
     rc = lib().oracle_model_seg(x.itemsize, MODES.get(mode, mode), _ptr(x), _ptr(y), _ptr(off), nseg,
-                                x_misalign, unroll, tile_elems, _ptr(out))
+                                x_misalign, unroll, tile_elems, _ptr(out), _ptr(viol))
     if rc != 0:
         raise ValueError("oracle_model_seg rejected its arguments")
-    return out
+    return (out, viol[:max(nseg, 0)].copy()) if with_violations else out

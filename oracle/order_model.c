@@ -153,7 +153,7 @@ static int valid_common(int dtype, int mode, int is_dot, int U) {
 
 int oracle_model_single(int dtype, int mode, const void* x, const void* y, int64_t n,
                         int x_misalign, int block_threads, int unroll, int grid_blocks,
-                        double* out2) {
+                        double* out2, double* viol) {
   if (!valid_common(dtype, mode, y != NULL, unroll) || n < 0 || (!x && n > 0)) return -1;
   if (block_threads < 64 || block_threads > 1024 || block_threads % 64) return -1;
   if (grid_blocks < 1 || (int64_t)grid_blocks * block_threads > ((int64_t)1 << 26)) return -1;
@@ -161,17 +161,17 @@ int oracle_model_single(int dtype, int mode, const void* x, const void* y, int64
   int is_dot = y != NULL;
   if (dtype == 8)
     return m64_single(mode, is_dot, (const double*)x, (const double*)y, n, x_misalign,
-                      block_threads, unroll, grid_blocks, out2);
+                      block_threads, unroll, grid_blocks, out2, viol);
   if (mode == MODE_WIDE)
     return mw_single(mode, is_dot, (const float*)x, (const float*)y, n, x_misalign,
-                     block_threads, unroll, grid_blocks, out2);
+                     block_threads, unroll, grid_blocks, out2, viol);
   return m32_single(mode, is_dot, (const float*)x, (const float*)y, n, x_misalign,
-                    block_threads, unroll, grid_blocks, out2);
+                    block_threads, unroll, grid_blocks, out2, viol);
 }
 
 int oracle_model_seg(int dtype, int mode, const void* x, const void* y,
                      const int64_t* offsets, int64_t nseg, int x_misalign,
-                     int unroll, int64_t tile_elems, double* out) {
+                     int unroll, int64_t tile_elems, double* out, double* viol) {
   if (!valid_common(dtype, mode, y != NULL, unroll) || nseg < 0 || !offsets) return -1;
   if (tile_elems <= 0 || tile_elems % (64 * (16 / dtype))) return -1;
   if (x_misalign < 0 || x_misalign >= 16 / dtype) return -1;
@@ -181,10 +181,10 @@ int oracle_model_seg(int dtype, int mode, const void* x, const void* y,
   int is_dot = y != NULL;
   if (dtype == 8)
     return m64_seg(mode, is_dot, (const double*)x, (const double*)y, offsets, nseg, x_misalign,
-                   unroll, tile_elems, out);
+                   unroll, tile_elems, out, viol);
   if (mode == MODE_WIDE)
     return mw_seg(mode, is_dot, (const float*)x, (const float*)y, offsets, nseg, x_misalign,
-                  unroll, tile_elems, out);
+                  unroll, tile_elems, out, viol);
   return m32_seg(mode, is_dot, (const float*)x, (const float*)y, offsets, nseg, x_misalign,
-                 unroll, tile_elems, out);
+                 unroll, tile_elems, out, viol);
 }

@@ -95,19 +95,24 @@ void   oracle_dott_f64(const double* x, const double* y, int64_t n, double* out2
  * boundary: (W - (x_misalign + o) mod W) mod W, capped at the range length,
  * with W = 16/dtype.
  * out2: {value, error} as binary64 (the binary32 results widen exactly).
+ * viol (may be NULL): for the fast forms (1, 5), the sum of |item| over the
+ * per-lane steps where Theorem 1's condition |s| >= |item| fails with
+ * s != 0, in binary64; +0 for the other modes. Only those steps can lose
+ * part of their round-off, each at most u(1 + 2u)|item|.
  * Returns 0, or -1 for invalid arguments or allocation failure.           */
 int oracle_model_single(int dtype, int mode, const void* x, const void* y, int64_t n,
                         int x_misalign, int block_threads, int unroll, int grid_blocks,
-                        double* out2);
+                        double* out2, double* viol);
 /* Segmented order model. offsets[0..nseg] (int64, non-decreasing), element
  * offsets into x (and y). tile_elems must be a multiple of 64*16/dtype.
  * Which wave processes which tile does not change any bit of the result
  * (a tile's pair depends only on its elements, and the tiles of a segment
  * are combined in tile order), so grid and block sizes are not inputs.
- * out: 2*nseg doubles, {value, error} per segment. */
+ * out: 2*nseg doubles, {value, error} per segment. viol (may be NULL):
+ * nseg doubles, the single-vector model's viol per segment. */
 int oracle_model_seg(int dtype, int mode, const void* x, const void* y,
                      const int64_t* offsets, int64_t nseg, int x_misalign,
-                     int unroll, int64_t tile_elems, double* out);
+                     int unroll, int64_t tile_elems, double* out, double* viol);
 
 #ifdef __cplusplus
 }

@@ -23,6 +23,7 @@ import torch
 
 import oracle
 import paper_1401_0248_amd as tf
+from oracle import bounds
 import synth
 from gpu_helpers import DEV, pair, same_bits, to_dev
 
@@ -105,8 +106,12 @@ def test_illconditioned_bench_workload(illcond, dtype):
             got_default = pair(tf.dot(xd, yd, mode))
             got = pair(tf.dot(xd, yd, mode, lc))
             assert same_bits(got, got_default)
-            want = oracle.model_single(mode, x, y, mis, bt, un, gb)
+            want, sv = oracle.model_single(mode, x, y, mis, bt, un, gb, with_violations=True)
             assert same_bits(got, want), (d, mode, got, list(want))
+            # within the bound of the launch's own tree (the fast form's
+            # widened by the steps that break Theorem 1's condition)
+            assert abs(ex.diff(*got)) <= bounds.single_bound(dtype, N_ILL, bt, un, gb, ex.A, sv), \
+                (d, mode, got)
             if mode == "rigorous":
                 assert abs(ex.diff(*got)) <= 4 * N_ILL * u * u * ex.A, (d, got)
         # the plain value of the same launch is the twofold value
@@ -138,6 +143,9 @@ def test_one_gib_dot_f64():
     u = _u(np.float64)
     v, e = pair(tf.dot(xd, yd, "rigorous"))
     assert abs(ex.diff(v, e)) <= 4 * n * u * u * ex.A
+    lc = tf.default_launch(0, 8, True, "rigorous", n)
+    assert abs(ex.diff(v, e)) <= bounds.single_bound(np.float64, n, lc.block_threads, lc.unroll,
+                                                     lc.grid_blocks, ex.A)
     lc = tf.Launch(512, 2, 256, 0, 0)
     got = pair(tf.dot(xd, yd, "rigorous", lc))
     assert same_bits(got, oracle.model_single("rigorous", x, y, mis, 512, 2, 256))
@@ -213,6 +221,7 @@ def test_segmented_full_batch_sampled(dtype):
         ex = oracle.Exact(xs, ys)
         assert abs(ex.diff(*got[s])) <= 4 * (b - a) * u * u * ex.A, s
         lr, lf = lcs["rigorous"], lcs["fast"]
+        assert abs(ex.diff(*got[s])) <= bounds.segment_bound(dtype, b - a, lr.tile_elems, ex.A), s
         want = oracle.model_seg("rigorous", xs, [0, b - a], ys, smis, lr.unroll, lr.tile_elems)
         assert same_bits(got[s], want[0]), (s, b - a)
         wantf = oracle.model_seg("fast", xs, [0, b - a], ys, smis, lf.unroll, lf.tile_elems)

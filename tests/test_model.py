@@ -225,3 +225,105 @@ def test_model_rejects_bad_arguments():
         oracle.model_seg("rigorous", x, [0, 5, 3], None, 0, 1, 128)
     with pytest.raises(ValueError):
         oracle.model_seg("rigorous", x, [0, 10], None, 0, 1, 100)
+
+
+# ---- launch-specific error bounds (oracle.bounds) ----------------------------
+from oracle import bounds  # noqa: E402
+
+
+_DATA = {}
+
+
+def _datasets(dtype, n, seed):
+    key = (np.dtype(dtype).name, n, seed)
+    if key not in _DATA:
+        sets = [("uniform",) + tuple(synth.uniform(seed, n, dtype, count=2)),
+                ("illcond",) + tuple(synth.illcond_dot(synth.illcond_seed(16), n, 1e16, dtype))]
+        if dtype == np.float32:
+            sets.append(("scaled",) + tuple(synth.scaled(seed, n)))
+        _DATA[key] = sets
+    return _DATA[key]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_rigorous_within_tree_bound(dtype, launch):
+    """The rigorous model result lies within the bound of its own tree, for
+    sums and dots, on uniform, ill-conditioned and scaled data."""
+    bt, U, gb = launch
+    n = 1 << 14
+    for name, x, y in _datasets(dtype, n, 7):
+        for yy in (None, y):
+            ex = oracle.Exact(x, yy)
+            got = oracle.model_single("rigorous", x, yy, 1, bt, U, gb)
+            b = bounds.single_bound(dtype, n, bt, U, gb, ex.A)
+            assert abs(ex.diff(got[0], got[1])) <= b, (name, yy is None)
+            assert b <= 4 * n * bounds.unit_roundoff(dtype) ** 2 * ex.A or gb * bt < 256
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_fast_within_violation_bound(dtype, launch):
+    """The fast model result lies within the tree bound widened by the loss
+    of the steps that break Theorem 1's condition, as the model counts them;
+    the rigorous form counts none."""
+    bt, U, gb = launch
+    n = 1 << 14
+    for name, x, y in _datasets(dtype, n, 8):
+        for yy in (None, y):
+            ex = oracle.Exact(x, yy)
+            got, sv = oracle.model_single("fast", x, yy, 0, bt, U, gb, with_violations=True)
+            b = bounds.single_bound(dtype, n, bt, U, gb, ex.A, fast_violations=sv)
+            assert abs(ex.diff(got[0], got[1])) <= b, (name, yy is None, sv)
+            _, sv_rig = oracle.model_single("rigorous", x, yy, 0, bt, U, gb, with_violations=True)
+            assert sv_rig == 0.0
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_fast_equals_rigorous_without_violations(dtype):
+    """Where no chain step breaks Theorem 1's condition, fast-two-sum's
+    round-off is exact, so the fast pair equals the rigorous pair bit for
+    bit. Positive items of decreasing size along every chain give such data;
+    random signs give violations, and then the pairs may differ only in e."""
+    n = 1 << 13
+    rng = np.random.default_rng(12)
+    x = (np.exp2(-np.arange(n) / 64.0) * (1 + rng.random(n))).astype(dtype)
+    y = np.ones(n, dtype=dtype)
+    for yy in (None, y):
+        f, sv = oracle.model_single("fast", x, yy, 0, 256, 2, 2, with_violations=True)
+        r = oracle.model_single("rigorous", x, yy, 0, 256, 2, 2)
+        assert sv == 0.0
+        assert f[0] == r[0] and f[1] == r[1]
+    z = rng.standard_normal(n).astype(dtype)
+    f, sv = oracle.model_single("fast", z, None, 0, 256, 2, 2, with_violations=True)
+    r = oracle.model_single("rigorous", z, None, 0, 256, 2, 2)
+    assert sv > 0.0 and f[0] == r[0]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_segments_within_tile_bound(dtype):
+    W = 16 // np.dtype(dtype).itemsize
+    ts = 64 * W * 4
+    lengths = synth.segment_lengths(5, 80, max_len=1 << 14)
+    off = synth.offsets_from_lengths(lengths)
+    x, y = synth.illcond_dot(synth.illcond_seed(12), int(off[-1]), 1e12, dtype)
+    for mode in ("rigorous", "fast"):
+        got, sv = oracle.model_seg(mode, x, off, y, 0, 4, ts, with_violations=True)
+        for s in range(len(lengths)):
+            a, b = off[s], off[s + 1]
+            ex = oracle.Exact(x[a:b], y[a:b])
+            bd = bounds.segment_bound(dtype, b - a, ts, ex.A, fast_violations=sv[s])
+            assert abs(ex.diff(*got[s])) <= bd, (mode, s)
+
+
+def test_tree_bound_depths():
+    """Depth bookkeeping on hand-counted launches."""
+    # binary64, 1 block of 64 lanes, n = 64*2*10 elements: 10 vectors per
+    # lane (+2 for head and tail); combines: 1 chain merge + 6 wave levels
+    assert bounds.single_depths(np.float64, 1280, 64, 1, 1) == (11 + 2, 7)
+    # binary32, 4 blocks of 256: + 3 block levels, + 1 strided + 6 + 3 in pass 2
+    Lc, D = bounds.single_depths(np.float32, 4096 * 4, 256, 4, 4)
+    assert D == 3 + 6 + 3 + 1 + 6 + 3
+    assert Lc == -(-(4096 + 1) // 1024) + 2
+    # a segment of three tiles: 3 + 6 inside the tile, 1 + 6 across tiles
+    assert bounds.segment_depths(np.float32, 3 * 1024, 1024) == (-(-257 // 64) + 2, 3 + 6 + 1 + 6)
