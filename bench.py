@@ -370,6 +370,15 @@ def segmented_batch(torch, tf, dev):
                          "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
                          "launch": plan.launch.as_dict()})
             log("  %s %s %.3f ms %.1f GB/s" % (np.dtype(dtype).name, form, t * 1e3, nbytes / t / 1e9))
+            if form == "rigorous":
+                # the precision monitor over the batch's results (tau = 2^-20)
+                od = torch.from_numpy(np.asarray(off, dtype=np.int64)).to(dev)
+                fl = torch.empty(plan.nseg, dtype=torch.int32, device=dev)
+                nf = torch.empty((), dtype=torch.int64, device=dev)
+                tm, _ = graph_time(torch, lambda: (tf.monitor(out, 2.0 ** -20, offsets=od, flags=fl,
+                                                              nflagged=nf), 1)[1])
+                rows[-1]["monitor_us"] = round(tm * 1e6, 2)
+                rows[-1]["monitor_flagged"] = int(nf.item())
             plan.close()
         del both, x, y
         torch.cuda.empty_cache()

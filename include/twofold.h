@@ -218,6 +218,32 @@ int twofold_seg_plan_execute(const twofold_seg_plan_t* plan, const void* x, cons
                              void* out, void* ws, size_t ws_bytes, void* stream);
 int twofold_seg_plan_destroy(twofold_seg_plan_t* plan);
 
+/* ---- precision monitor ----------------------------------------------------
+ * The paper proposes to stop a computation whose error term gets too large,
+ * as a sign that the precision in use is not enough ("Algorithms", remarks
+ * after the rigorous form), and expects twofold summation to work for N
+ * below 1/u ("Overview"). twofold_monitor applies both to count results
+ * already on the device:
+ *   pairs:    device twofold_f32_t[count] (dtype 4) or twofold_f64_t[count]
+ *             (dtype 8), e.g. the out array of a segmented call;
+ *   offsets:  device int64[count + 1]; result i has length
+ *             offsets[i+1] - offsets[i]. NULL: every result has length n;
+ *   tau:      finite, >= 0;
+ *   flags:    device uint32[count], written: TWOFOLD_FLAG_ERROR when
+ *             |error| > tau*|value|, TWOFOLD_FLAG_LENGTH when the length is
+ *             at least 1/u (2^24 for dtype 4, 2^53 for dtype 8),
+ *             TWOFOLD_FLAG_NONFINITE when value or error is Inf or NaN (then
+ *             TWOFOLD_FLAG_ERROR is not set). Comparisons are made in
+ *             binary64 on the exactly widened pair, tau*|value| rounded once;
+ *   nflagged: device int64, written: the number of nonzero flags.
+ * Asynchronous on stream, no workspace, capturable (two kernels: one
+ * clears *nflagged, one writes the flags and adds up the count). */
+#define TWOFOLD_FLAG_ERROR 1u
+#define TWOFOLD_FLAG_LENGTH 2u
+#define TWOFOLD_FLAG_NONFINITE 4u
+int twofold_monitor(int dtype, const void* pairs, int64_t count, const int64_t* offsets, int64_t n,
+                    double tau, uint32_t* flags, int64_t* nflagged, void* stream);
+
 /* ---- instruments ----------------------------------------------------------
  * Memory-only probe (the paper's read1/read2, section "Memory reading"):
  * streams x (and y, if not NULL), nbytes each, with 16-byte loads in the

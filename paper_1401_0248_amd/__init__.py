@@ -14,12 +14,13 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (FAST, FAST_ROUNDED, KAHAN, PLAIN, RIGOROUS, RIGOROUS_ROUNDED, WIDE, Launch,
-                   TwofoldError, check)
+from ._lib import (FAST, FAST_ROUNDED, FLAG_ERROR, FLAG_LENGTH, FLAG_NONFINITE, KAHAN, PLAIN,
+                   RIGOROUS, RIGOROUS_ROUNDED, WIDE, Launch, TwofoldError, check)
 
 __all__ = [
-    "sum", "dot", "sumd", "dotd", "segsum", "segdot", "SegPlan", "Launch",
+    "sum", "dot", "sumd", "dotd", "segsum", "segdot", "SegPlan", "Launch", "monitor",
     "TwofoldError", "workspace", "default_launch", "probe_read", "probe_compute",
+    "FLAG_ERROR", "FLAG_LENGTH", "FLAG_NONFINITE",
     "PLAIN", "FAST", "RIGOROUS", "WIDE", "KAHAN", "FAST_ROUNDED", "RIGOROUS_ROUNDED", "mode_id",
 ]
 
@@ -247,6 +248,39 @@ class SegPlan:
             self.close()
         except Exception:
             pass
+
+
+def monitor(pairs, tau, offsets=None, n=None, flags=None, nflagged=None):
+    """Precision monitor (twofold_monitor): pairs is a (count, 2) float32 or
+    float64 device tensor of (value, error) results, e.g. a segmented
+    call's output; lengths come from offsets (device int64, count + 1
+    entries) or are all n. Returns (flags, nflagged): uint32-valued flags
+    (stored as int32) per result and the count of flagged results (int64
+    device scalar), both on the device."""
+    L = _lib.load()
+    if not pairs.is_cuda or pairs.dtype not in (torch.float32, torch.float64) or \
+            pairs.dim() != 2 or pairs.shape[1] != 2 or not pairs.is_contiguous():
+        raise ValueError("pairs must be a contiguous (count, 2) float32 or float64 GPU tensor")
+    if offsets is None and n is None:
+        raise ValueError("give offsets or n")
+    dev = pairs.device
+    count = pairs.shape[0]
+    if offsets is not None:
+        if offsets.dtype != torch.int64 or offsets.dim() != 1 or not offsets.is_contiguous() or \
+                offsets.numel() != count + 1 or offsets.device != dev:
+            raise ValueError("offsets must be a contiguous int64 tensor of count + 1 entries on "
+                             "the pairs' device")
+    if flags is None:
+        flags = torch.empty(count, dtype=torch.int32, device=dev)
+    if nflagged is None:
+        nflagged = torch.empty((), dtype=torch.int64, device=dev)
+    check("twofold_monitor", L.twofold_monitor(
+        pairs.element_size(), ctypes.c_void_p(pairs.data_ptr()) if count else None, count,
+        ctypes.c_void_p(offsets.data_ptr()) if offsets is not None else None,
+        0 if n is None else int(n), float(tau),
+        ctypes.c_void_p(flags.data_ptr()) if count else None, ctypes.c_void_p(nflagged.data_ptr()),
+        _stream_ptr(dev)))
+    return flags, nflagged
 
 
 def probe_read(x, y=None, launch=None, sink=None):

@@ -11,6 +11,7 @@ from . import build as _build
 
 OK, EINVAL, EWORKSPACE, EHIP, EALIGN, EOFFSETS = 0, -1, -2, -3, -4, -5
 PLAIN, FAST, RIGOROUS, WIDE, KAHAN, FAST_ROUNDED, RIGOROUS_ROUNDED = 0, 1, 2, 3, 4, 5, 6
+FLAG_ERROR, FLAG_LENGTH, FLAG_NONFINITE = 1, 2, 4
 
 # Every symbol the public header declares, with (restype, argtypes).
 _vp = ctypes.c_void_p
@@ -50,6 +51,7 @@ SIGNATURES = {
     "twofold_seg_plan_get_launch": (_int, [_vp, _LP]),
     "twofold_seg_plan_execute": (_int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "twofold_seg_plan_destroy": (_int, [_vp]),
+    "twofold_monitor": (_int, [_int, _vp, _i64, _vp, _i64, ctypes.c_double, _vp, _vp, _vp]),
     "twofold_probe_read": (_int, [_vp, _vp, _i64, _LP, _vp, _vp]),
     "twofold_probe_compute": (_int, [_int, _int, _int, _vp, _i64, _LP, _vp, _vp]),
     "twofold_strerror": (ctypes.c_char_p, [_int]),
