@@ -228,3 +228,53 @@ def test_segmented_full_batch_sampled(dtype):
         assert same_bits(gotf[s], wantf[0]), (s, b - a)
     del both, host
     torch.cuda.empty_cache()
+
+
+# binary32 sums above 2^31 elements: (block_threads, unroll, max_blocks) and
+# the segmented (unroll, tile) of the tuned table, restated like the others
+BIG_SUM = (256, 8, 256)
+BIG_SEG_SUM = (8, 32768)
+
+
+def test_beyond_2e31_elements():
+    """A binary32 vector of 2^31 + 1027 elements (8 GiB): 64-bit indexing in
+    the single-vector and segmented paths. Uniform data on the 2^-23 grid:
+    v + e equals the exact sum, and every pair equals the order model's."""
+    n = (1 << 31) + (1 << 10) + 3
+    _note("2^31 + 1027 binary32 elements: generating")
+    x = np.empty(n, dtype=np.float32)
+    xd = torch.empty(n, dtype=torch.float32, device=DEV)
+    i = 0
+    for c in synth.uniform_chunks(21, n, np.float32, chunk=1 << 26):
+        x[i:i + c.size] = c
+        xd[i:i + c.size].copy_(torch.from_numpy(c))
+        i += c.size
+    mis = (xd.data_ptr() % 16) // 4
+    bt, un, gb = BIG_SUM
+    lib = tf.default_launch(0, 4, False, "rigorous", n)
+    assert (lib.block_threads, lib.unroll, lib.grid_blocks) == (bt, un, gb), \
+        "tuned table changed: update BIG_SUM (result bits depend on it)"
+    ex = oracle.Exact(x)
+    lc = tf.Launch(bt, un, gb, 0, 0)
+    for mode in ("rigorous", "fast"):
+        _note("2^31 + 1027: %s sum" % mode)
+        got = pair(tf.sum(xd, mode, lc))
+        assert ex.diff(*got) == 0.0, mode
+        assert same_bits(got, oracle.model_single(mode, x, None, mis, bt, un, gb)), mode
+    assert ex.diff(*pair(tf.sum(xd, "rigorous"))) == 0.0
+    # three segments, the middle one across element 2^31
+    off = np.array([0, (1 << 30) + 5, (1 << 31) + 7, n], dtype=np.int64)
+    su, sts = BIG_SEG_SUM
+    lib = tf.default_launch(1, 4, False, "rigorous", n, 3)
+    assert (lib.unroll, lib.tile_elems) == (su, sts), \
+        "tuned table changed: update BIG_SEG_SUM (result bits depend on it)"
+    _note("2^31 + 1027: segmented sum")
+    plan = tf.SegPlan(off, torch.float32, False, "rigorous")
+    got = plan.execute(xd).double().cpu().numpy()
+    want = oracle.model_seg("rigorous", x, off, None, mis, su, sts)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+    for s in range(3):
+        assert oracle.Exact(x[off[s]:off[s + 1]]).diff(*got[s]) == 0.0, s
+    plan.close()
+    del xd
+    torch.cuda.empty_cache()
