@@ -55,8 +55,7 @@ def gpu_results(dev_in, tf):
     for k, (xd, yd) in dev_in.items():
         for mode in ("plain", "fast", "rigorous"):
             res[k + (mode,)] = tf.dot(xd, yd, mode).double().cpu().numpy()
-        if k[0] == np.float32:
-            res[k + ("dotd",)] = tf.dotd(xd, yd).cpu().numpy()
+        res[k + ("dotd",)] = tf.dotd(xd, yd).cpu().numpy()
     return res
 
 
@@ -134,9 +133,11 @@ def oracle_leg(host, gpu, launches):
                 rows.setdefault("%s_%s_value" % (key, mode), []).append(abs(dv) / ex.A)
                 rows.setdefault("%s_%s_q" % (key, mode), []).append(
                     p[1] / -dv if dv else float("nan"))
+        p = gpu[(dt, d, "dotd")]
         if dt == np.float32:
-            p = gpu[(dt, d, "dotd")]
             rows.setdefault("f32data_f64plain", []).append(abs(ex.diff(p[0])) / ex.A)
+        else:
+            rows.setdefault("f64_double_word", []).append(abs(ex.diff(p[0], p[1])) / ex.A)
         rows.setdefault("cond_" + key, []).append(2 * ex.A / abs(ex.S) if ex.S else float("inf"))
     acc = {"measure": "median over conditions of |v + e - S| / sum|x y| (*_value: |v - S| / "
                       "sum|x y|; *_q: e / (S - v); *_over_tree_bound: the largest |v + e - S| "
@@ -170,13 +171,16 @@ def precision_study(torch, tf, dev, with_oracle):
     x64, y64 = xd.double(), yd.double()
     L = tf._lib.load()
     ws = tf.Workspace(max(L.twofold_workspace_bytes_single(sz, 1, m, n, None)
-                          for sz, m in ((4, 0), (4, 1), (4, 2), (4, 3), (8, 0), (8, 2))), dev)
+                          for sz, m in ((4, 0), (4, 1), (4, 2), (4, 3), (8, 0), (8, 2), (8, 3))),
+                      dev)
     forms = [("f32 plain", lambda o: tf.dot(xd, yd, "plain", out=o, ws=ws), 4),
              ("f32 fast twofold", lambda o: tf.dot(xd, yd, "fast", out=o, ws=ws), 4),
              ("f32 rigorous twofold", lambda o: tf.dot(xd, yd, "rigorous", out=o, ws=ws), 4),
              ("f64 plain on f32 data (dotd)", lambda o: tf.dotd(xd, yd, out=o, ws=ws), 8),
              ("f64 plain on an f64 copy", lambda o: tf.dot(x64, y64, "plain", out=o, ws=ws), 8),
              ("f64 rigorous on an f64 copy", lambda o: tf.dot(x64, y64, "rigorous", out=o, ws=ws),
+              8),
+             ("f64 double-word (dotd) on an f64 copy", lambda o: tf.dotd(x64, y64, out=o, ws=ws),
               8)]
     rows, results = [], {}
     for name, fn, osz in forms:
@@ -293,7 +297,7 @@ def roofline_sweep(torch, tf, dev):
             big = n * size >= (1 << 28)
             reps = 4 if big else 50  # calls per graph: amortizes the replay's own start
             for op in ("sum", "dot"):
-                forms = FORMS + ("kahan",) + (("wide",) if dtype == np.float32 else ())
+                forms = FORMS + ("kahan", "wide")
                 if op == "dot":
                     forms += ("fast_rounded", "rigorous_rounded")
                 for form in forms:

@@ -28,8 +28,14 @@
  * rounding: p = fl(x*y), pi = fma(x, y, -p), x*y = p + pi exactly unless the
  * product underflows; p is the item and pi joins the error
  * (fast: e += pi - c; rigorous: e += (ds + dy) + pi).
- * The paper's sumd/dotd (binary32 data, binary64 accumulator, section
- * "Performance", function list) are twofold_sumd_f32 / twofold_dotd_f32.
+ * The paper's sumd/dotd (a wider accumulator, section "Performance",
+ * function list) are twofold_sumd_* / twofold_dotd_* (mode TWOFOLD_WIDE):
+ * binary32 data summed in binary64 as the paper does, and binary64 data,
+ * for which the paper used quad precision, summed in double-word
+ * (double-double) arithmetic: the accumulator (h, l) takes each item with
+ * DWPlusFP, or each exact product p + pi with AccurateDWPlusDW, and pairs
+ * combine with AccurateDWPlusDW (Joldes, Muller, Popescu, ACM TOMS 2017,
+ * Algorithms 4 and 6); the result's value is h and its error l.
  *
  * All arithmetic is IEEE round-to-nearest-even with no contraction other
  * than the one FMA above; binary32 subnormals are kept. A twofold value is
@@ -39,9 +45,10 @@
  * T is float or double, W = 16/sizeof(T) (elements per 16-byte vector).
  * Every chain starts at (+0, +0). combine((s1,e1),(s2,e2)) is two-sum
  * (Theorem 2, all six operations) of s1, s2 giving (x, y), then
- * error (e1 + e2) + y, value x; in plain and wide modes it is
- * (s1 + s2, +0). The Kahan step keeps e = -c: yk = item + e, t = s + yk,
- * e = yk - (t - s), s = t (exactly Example 2's operations, negated).
+ * error (e1 + e2) + y, value x; in plain and binary32 wide modes it is
+ * (s1 + s2, +0); in binary64 wide mode it is AccurateDWPlusDW. The Kahan
+ * step keeps e = -c: yk = item + e, t = s + yk, e = yk - (t - s), s = t
+ * (exactly Example 2's operations, negated).
  * Single vector, launch (block_threads BT, unroll U, grid_blocks GB),
  * L = GB*BT lanes, lane g = block*BT + thread:
  *   1. head: the h = min(n, elements before x's first 16-byte boundary)
@@ -71,8 +78,16 @@
  *   lanes, lane l starting at (+0,+0) and combining tiles l, l+64, ... in
  *   tile order, then step 5, then step 8; an empty segment gives (+0,+0).
  *   Which wave handles which tile does not change the result.
- * Wide (sumd/dotd): as above with binary64 chains over widened binary32
- * data and the plain combine; results are binary64 pairs with error +0.
+ * Wide (sumd/dotd): binary32 data: as above with binary64 chains over
+ * widened binary32 data and the plain combine; results are binary64 pairs
+ * with error +0. binary64 data: as above with double-word chains: the step
+ * (h, l) = DWPlusFP((h, l), x), for dots AccurateDWPlusDW((h, l), (p, pi))
+ * with p = fl(x*y), pi = fma(x, y, -p); combine is AccurateDWPlusDW, written
+ * out as (sh, sl) = two-sum(h1, h2), (th, tl) = two-sum(l1, l2),
+ * c = sl + th, (vh, vl) = fast-two-sum(sh, c), w = tl + vl,
+ * (h, l) = fast-two-sum(vh, w); DWPlusFP as (sh, sl) = two-sum(h, x),
+ * v = l + sl, (h, l) = fast-two-sum(sh, v); fast-two-sum(a, b) is s = a + b,
+ * (s, b - (s - a)).
  *
  * ---- Conventions --------------------------------------------------------
  * Pointers: x, y, out, offsets and ws are device pointers (hipMalloc or
@@ -115,7 +130,8 @@ enum {
   TWOFOLD_PLAIN = 0,
   TWOFOLD_FAST = 1,
   TWOFOLD_RIGOROUS = 2,
-  TWOFOLD_WIDE = 3, /* binary32 data, binary64 accumulator (sumd/dotd, plans) */
+  TWOFOLD_WIDE = 3, /* the wider accumulator (sumd/dotd, plans): binary64 for
+                       binary32 data, double-word for binary64 data */
   TWOFOLD_KAHAN = 4,
   TWOFOLD_FAST_ROUNDED = 5,
   TWOFOLD_RIGOROUS_ROUNDED = 6
@@ -178,12 +194,19 @@ int twofold_sumd_f32(const float* x, int64_t n, const twofold_launch_t* launch,
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
 int twofold_dotd_f32(const float* x, const float* y, int64_t n, const twofold_launch_t* launch,
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
+/* The same for binary64 data, in double-word arithmetic (the paper's quad
+ * accumulator, see above): out = (h, l), h + l the double-word sum. */
+int twofold_sumd_f64(const double* x, int64_t n, const twofold_launch_t* launch,
+                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
+int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_launch_t* launch,
+                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- segmented (CSR) batches: nseg pairs into out[0..nseg) ---------------
  * offsets: device int64[nseg + 1], non-decreasing, offsets[0] >= 0 and
  * offsets[nseg] <= n_total (the length of x and y). Checked on the device:
  * on violation every out[s] is NaN.
- * mode TWOFOLD_WIDE is not accepted here (see the plan interface). */
+ * mode TWOFOLD_WIDE is accepted here for binary64 data only (binary32
+ * data: see the plan interface). */
 int twofold_segsum_f32(const float* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
                        int mode, const twofold_launch_t* launch, twofold_f32_t* out, void* ws,
                        size_t ws_bytes, void* stream);
@@ -203,7 +226,7 @@ int twofold_segdot_f64(const double* x, const double* y, int64_t n_total, const 
  * device memory owned by the plan, with the plan's per-segment completion
  * (synchronous; not capturable). The workspace of an execute holds the
  * pairs of the tiles of multi-tile segments.
- * dtype 4 or 8; mode TWOFOLD_* (WIDE only with dtype 4).
+ * dtype 4 or 8; mode TWOFOLD_* (ROUNDED forms only for dots).
  * execute: the tile kernel (persistent waves) and the combine kernel on
  * stream, no host work in between; out is twofold_f32_t[nseg] for
  * dtype 4 modes PLAIN/FAST/RIGOROUS, twofold_f64_t[nseg] otherwise; y must

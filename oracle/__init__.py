@@ -13,7 +13,9 @@ Three parts, all in plain C (``liboracle.so``, built by ``oracle/build.py``):
 * ``seq``: the paper's sequential loops (section "Algorithms": Example 1
   ``sumtf``, Example 2 ``sumk``, Example 3 ``sumt`` and direct ``sum``, the
   double accumulator ``sumd``, and the dot rule that puts ``a[i]*b[i]`` in
-  place of ``data[i]``), plus the dot with an FMA remainder.
+  place of ``data[i]``), plus the dot with an FMA remainder, and for
+  binary64 data the double-word accumulator ``sumdd``/``dotdd`` standing in
+  for the paper's quad one (``dw_plus_fp``/``dw_plus_dw`` expose its steps).
 * ``model_single`` / ``model_seg``: the same per-element steps applied in the
   GPU library's documented reduction order, for bitwise comparisons.
 """
@@ -71,6 +73,15 @@ def lib():
         L.oracle_sumd_f32.argtypes = [vp, i64]
         L.oracle_dotd_f32.restype = ctypes.c_double
         L.oracle_dotd_f32.argtypes = [vp, vp, i64]
+        L.oracle_sumdd_f64.restype = None
+        L.oracle_sumdd_f64.argtypes = [vp, i64, vp]
+        L.oracle_dotdd_f64.restype = None
+        L.oracle_dotdd_f64.argtypes = [vp, vp, i64, vp]
+        cd = ctypes.c_double
+        L.oracle_dw_plus_fp.restype = None
+        L.oracle_dw_plus_fp.argtypes = [cd, cd, cd, vp]
+        L.oracle_dw_plus_dw.restype = None
+        L.oracle_dw_plus_dw.argtypes = [cd, cd, cd, cd, vp]
         L.oracle_model_single.restype = i32
         L.oracle_model_single.argtypes = [i32, i32, vp, vp, i64, i32, i32, i32, i32, vp, vp]
         L.oracle_model_seg.restype = i32
@@ -160,11 +171,25 @@ def seq(kind, x, y=None):
         t = np.float64 if kind == "dotd" else x.dtype.type
         return t(v), t(0)
     out = np.zeros(2, dtype=x.dtype)
-    if kind in ("sumtf", "sumt", "sumk_pair"):
+    if kind in ("sumtf", "sumt", "sumk_pair", "sumdd"):
         f(_ptr(x), x.size, _ptr(out))
     else:
         f(_ptr(x), _ptr(y), x.size, _ptr(out))
     return out[0], out[1]
+
+
+def dw_plus_fp(h, l, y):
+    """DWPlusFP (Joldes, Muller, Popescu 2017, Algorithm 4): (h, l) + y."""
+    out = np.zeros(2)
+    lib().oracle_dw_plus_fp(h, l, y, _ptr(out))
+    return float(out[0]), float(out[1])
+
+
+def dw_plus_dw(xh, xl, yh, yl):
+    """AccurateDWPlusDW (same paper, Algorithm 6): (xh, xl) + (yh, yl)."""
+    out = np.zeros(2)
+    lib().oracle_dw_plus_dw(xh, xl, yh, yl, _ptr(out))
+    return float(out[0]), float(out[1])
 
 
 def model_single(mode, x, y=None, x_misalign=0, block_threads=256, unroll=4, grid_blocks=1,

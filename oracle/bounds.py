@@ -102,3 +102,18 @@ def single_bound(dtype, n, block_threads, unroll, grid_blocks, A, fast_violation
 def segment_bound(dtype, seg_len, tile_elems, A, fast_violations=0.0):
     Lc, D = segment_depths(dtype, seg_len, tile_elems)
     return tree_bound(dtype, Lc, D, A, fast_violations)
+
+
+def dw_bound(Lc, D, A):
+    """Bound on |h + l - S| for the wide mode on binary64 data (double-word
+    chains and combines). Every double-word addition returns its operands'
+    exact sum up to a relative 3u^2 + 13u^3 (AccurateDWPlusDW; DWPlusFP is
+    within 2u^2), and an item lies under at most Lc + D additions (chain
+    steps after it, then combines), so the errors add up to at most
+    (Lc + D) (3u^2 + 13u^3) A, to first order; the denominator covers the
+    errors' own growth."""
+    u = unit_roundoff(np.float64)
+    r = (Lc + D) * (3 * u * u + 13 * u ** 3)
+    if r >= 1:
+        return math.inf
+    return r * A / (1 - r)

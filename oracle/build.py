@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["xacc.c", "paper_loops.c", "order_model.c"]
-DEPS = SOURCES + ["paper_loops.inc", "order_model.inc", "twofold_oracle.h"]
+DEPS = SOURCES + ["paper_loops.inc", "order_model.inc", "twofold_oracle.h", "dw.h"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 CFLAGS = [

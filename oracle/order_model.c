@@ -23,6 +23,8 @@
  *   8. finalize: binary64 results as they are; binary32 value fl32(V) and
  *      error fl32((V - value) + E), both operations in binary64 (error +0
  *      for the plain and wide modes, whose pairs carry no error).
+ * The wide mode on binary64 data keeps double-word chains and combines
+ * them with AccurateDWPlusDW in every step above (dw.h).
  * Segmented, tiles of TS elements (TS a multiple of 64*W): segment s has
  * ceil(len_s/TS) tiles; each tile is reduced by one 64-lane wave with
  * steps 1-5 on the tile's range; a one-tile segment's pair is finalized
@@ -34,6 +36,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include "dw.h"
 #include "twofold_oracle.h"
 
 #define MODE_PLAIN 0
@@ -43,12 +46,20 @@
 #define MODE_KAHAN 4
 #define MODE_FAST_ROUNDED 5
 #define MODE_RIGOROUS_ROUNDED 6
+/* The wide mode on binary64 data: a double-word accumulator (dw.h). The
+ * public mode number is MODE_WIDE for both data types; this one is the
+ * model's own name for the binary64 case. */
+#define MODE_DW 7
 #define HAS_ERROR(m) ((m) != MODE_PLAIN && (m) != MODE_WIDE)
 
 static void combine64(int mode, double* s1, double* e1, double s2, double e2) {
   if (!HAS_ERROR(mode)) {
     *s1 = *s1 + s2;
     *e1 = 0;
+    return;
+  }
+  if (mode == MODE_DW) {
+    dw_plus_dw(*s1, *e1, s2, e2, s1, e1);
     return;
   }
   double a = *s1, b = s2;
@@ -125,7 +136,9 @@ static void finalize(int mode, int tsize, double V, double E, double* out2) {
 #define A double
 #define FMA_T fma
 #define NAME(base) m64_##base
+#define WITH_DW 1
 #include "order_model.inc"
+#undef WITH_DW
 #undef T
 #undef A
 #undef FMA_T
@@ -145,7 +158,6 @@ static void finalize(int mode, int tsize, double V, double E, double* out2) {
 static int valid_common(int dtype, int mode, int is_dot, int U) {
   if (dtype != 4 && dtype != 8) return 0;
   if (mode < MODE_PLAIN || mode > MODE_RIGOROUS_ROUNDED) return 0;
-  if (mode == MODE_WIDE && dtype != 4) return 0;
   if ((mode == MODE_FAST_ROUNDED || mode == MODE_RIGOROUS_ROUNDED) && !is_dot) return 0;
   if (U < 1 || U > 64) return 0;
   return 1;
@@ -159,6 +171,7 @@ int oracle_model_single(int dtype, int mode, const void* x, const void* y, int64
   if (grid_blocks < 1 || (int64_t)grid_blocks * block_threads > ((int64_t)1 << 26)) return -1;
   if (x_misalign < 0 || x_misalign >= 16 / dtype) return -1;
   int is_dot = y != NULL;
+  if (dtype == 8 && mode == MODE_WIDE) mode = MODE_DW;
   if (dtype == 8)
     return m64_single(mode, is_dot, (const double*)x, (const double*)y, n, x_misalign,
                       block_threads, unroll, grid_blocks, out2, viol);
@@ -179,6 +192,7 @@ int oracle_model_seg(int dtype, int mode, const void* x, const void* y,
   for (int64_t s = 0; s < nseg; s++)
     if (offsets[s + 1] < offsets[s]) return -1;
   int is_dot = y != NULL;
+  if (dtype == 8 && mode == MODE_WIDE) mode = MODE_DW;
   if (dtype == 8)
     return m64_seg(mode, is_dot, (const double*)x, (const double*)y, offsets, nseg, x_misalign,
                    unroll, tile_elems, out, viol);

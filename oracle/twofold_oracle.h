@@ -68,6 +68,12 @@ void   oracle_dott_rounded_f32(const float* x, const float* y, int64_t n, float*
 void   oracle_dottf_f32(const float* x, const float* y, int64_t n, float* out2);
 void   oracle_dott_f32(const float* x, const float* y, int64_t n, float* out2);
 double oracle_dotd_f32(const float* x, const float* y, int64_t n);
+/* The wider accumulator for binary64 data: double-word (h, l) in place of
+ * the paper's quad (see dw.h); out2 = {h, l}. */
+void   oracle_sumdd_f64(const double* x, int64_t n, double* out2);
+void   oracle_dotdd_f64(const double* x, const double* y, int64_t n, double* out2);
+void   oracle_dw_plus_fp(double h, double l, double y, double* out2);
+void   oracle_dw_plus_dw(double xh, double xl, double yh, double yl, double* out2);
 
 double oracle_sum_f64(const double* x, int64_t n);
 double oracle_sumk_f64(const double* x, int64_t n);
@@ -83,8 +89,9 @@ void   oracle_dottf_f64(const double* x, const double* y, int64_t n, double* out
 void   oracle_dott_f64(const double* x, const double* y, int64_t n, double* out2);
 
 /* ---- 3. order model --------------------------------------------------------
- * mode: 0 plain, 1 fast, 2 rigorous, 3 wide (binary32 data, binary64
- * accumulator; paper's sumd/dotd), 4 Kahan (Example 2; the error is the
+ * mode: 0 plain, 1 fast, 2 rigorous, 3 wide (the paper's sumd/dotd:
+ * binary64 accumulator for binary32 data, double-word accumulator for
+ * binary64 data), 4 Kahan (Example 2; the error is the
  * negated correction), 5 fast and 6 rigorous with the rounded product as
  * the item (the paper's dot rule; dots only). dtype: 4 (binary32) or 8
  * (binary64).

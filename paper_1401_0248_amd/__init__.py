@@ -116,7 +116,7 @@ def _single(fn, x, y, mode, launch, out, ws, out_dtype):
     if y is not None:
         args.append(ctypes.c_void_p(y.data_ptr()))
     args.append(n)
-    if fn not in ("twofold_sumd_f32", "twofold_dotd_f32"):
+    if not fn.startswith(("twofold_sumd_", "twofold_dotd_")):
         args.append(m)
     args += [lp, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.ptr), ws.nbytes,
              _stream_ptr(dev)]
@@ -138,17 +138,18 @@ def dot(x, y, mode="rigorous", launch=None, out=None, ws=None):
 
 
 def sumd(x, launch=None, out=None, ws=None):
-    """Paper's sumd: float32 data summed in a float64 accumulator."""
-    if x.dtype != torch.float32:
-        raise TypeError("sumd takes float32 data")
-    return _single("twofold_sumd_f32", x, None, WIDE, launch, out, ws, torch.float64)
+    """Paper's sumd, the wider accumulator: float32 data summed in float64;
+    float64 data summed in double-word arithmetic (the paper used quad).
+    Returns a float64 tensor([value, error])."""
+    fn = "twofold_sumd_f32" if x.dtype == torch.float32 else "twofold_sumd_f64"
+    return _single(fn, x, None, WIDE, launch, out, ws, torch.float64)
 
 
 def dotd(x, y, launch=None, out=None, ws=None):
-    """Paper's dotd: float32 data, float64 products and accumulator."""
-    if x.dtype != torch.float32:
-        raise TypeError("dotd takes float32 data")
-    return _single("twofold_dotd_f32", x, y, WIDE, launch, out, ws, torch.float64)
+    """Paper's dotd: float32 data with float64 products and accumulator;
+    float64 data with exact products in a double-word accumulator."""
+    fn = "twofold_dotd_f32" if x.dtype == torch.float32 else "twofold_dotd_f64"
+    return _single(fn, x, y, WIDE, launch, out, ws, torch.float64)
 
 
 def _seg(x, y, offsets, mode, launch, out, ws):

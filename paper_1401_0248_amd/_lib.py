@@ -42,6 +42,8 @@ SIGNATURES = {
     "twofold_dot_f64": (_int, [_vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_sumd_f32": (_int, [_vp, _i64, _LP, _vp, _vp, _sz, _vp]),
     "twofold_dotd_f32": (_int, [_vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_sumd_f64": (_int, [_vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_dotd_f64": (_int, [_vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segsum_f32": (_int, [_vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segsum_f64": (_int, [_vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segdot_f32": (_int, [_vp, _vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),

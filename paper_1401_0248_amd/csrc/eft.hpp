@@ -15,6 +15,10 @@ namespace twofold {
 
 // kKahan: Example 2; kFastRounded / kRigorousRounded: the paper's own dot
 // rule (the rounded product is the item; its rounding is not tracked).
+// kWide is the paper's wider accumulator: for binary32 data a binary64 sum
+// (kWide itself); for binary64 data, where the paper used quad precision,
+// a double-word (double-double) sum, kDoubleDouble (internal only: the
+// public mode is TWOFOLD_WIDE for both data types).
 enum Mode : int {
   kPlain = 0,
   kFast = 1,
@@ -22,7 +26,8 @@ enum Mode : int {
   kWide = 3,
   kKahan = 4,
   kFastRounded = 5,
-  kRigorousRounded = 6
+  kRigorousRounded = 6,
+  kDoubleDouble = 7
 };
 
 // Modes whose pairs carry an error (all but plain and wide).
@@ -30,6 +35,44 @@ constexpr bool has_error(int m) { return m != kPlain && m != kWide; }
 
 __device__ __forceinline__ float fma_rn(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_rn(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---- double-word arithmetic (kDoubleDouble) -------------------------------
+// A double-word number is a pair (h, l) with h = fl(h + l). The additions
+// are the published algorithms of Joldes, Muller and Popescu ("Tight and
+// rigorous error bounds for basic building blocks of double-word
+// arithmetic", ACM TOMS 2017): DWPlusFP (their Algorithm 4, relative error
+// at most 2u^2) and AccurateDWPlusDW (their Algorithm 6, at most
+// 3u^2 + 13u^3), built from two-sum (Theorem 2) and fast-two-sum (Theorem 1).
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& d) {
+  s = a + b;
+  const double bp = s - a;
+  const double ap = s - bp;
+  d = (a - ap) + (b - bp);
+}
+
+__device__ __forceinline__ void fast_two_sum(double a, double b, double& s, double& d) {
+  s = a + b;
+  d = b - (s - a);
+}
+
+// (h, l) += y
+__device__ __forceinline__ void dw_add_fp(double& h, double& l, double y) {
+  double sh, sl;
+  two_sum(h, y, sh, sl);
+  const double v = l + sl;
+  fast_two_sum(sh, v, h, l);
+}
+
+// (h, l) += (yh, yl)
+__device__ __forceinline__ void dw_add_dw(double& h, double& l, double yh, double yl) {
+  double sh, sl, th, tl, vh, vl;
+  two_sum(h, yh, sh, sl);
+  two_sum(l, yl, th, tl);
+  const double c = sl + th;
+  fast_two_sum(sh, c, vh, vl);
+  const double w = tl + vl;
+  fast_two_sum(vh, w, h, l);
+}
 
 // One data item into one chain (s, e). T is the data type, A the
 // accumulator type (A == T except in kWide, where binary32 data is widened
@@ -39,6 +82,15 @@ __device__ __forceinline__ void step(A& s, A& e, T xv, T yv) {
   if constexpr (M == kWide) {
     A item = DOT ? static_cast<A>(xv) * static_cast<A>(yv) : static_cast<A>(xv);
     s = s + item;
+  } else if constexpr (M == kDoubleDouble) {
+    // (s, e) is the double-word accumulator; a dot adds the exact product
+    // p + pi as a double-word number.
+    if constexpr (DOT) {
+      const double p = xv * yv;
+      dw_add_dw(s, e, p, fma_rn(xv, yv, -p));
+    } else {
+      dw_add_fp(s, e, xv);
+    }
   } else if constexpr (M == kPlain) {
     T item = DOT ? xv * yv : xv;
     s = s + item;
@@ -85,12 +137,14 @@ __device__ __forceinline__ void step(A& s, A& e, T xv, T yv) {
 
 // combine((s1,e1),(s2,e2)): two-sum of the values with all six operations
 // of Theorem 2, then the errors and the two-sum remainder. Plain and wide
-// pairs carry no error.
+// pairs carry no error; double-word pairs are added with AccurateDWPlusDW.
 template <int M, typename A>
 __device__ __forceinline__ void combine(A& s1, A& e1, A s2, A e2) {
   if constexpr (!has_error(M)) {
     s1 = s1 + s2;
     e1 = A(0);
+  } else if constexpr (M == kDoubleDouble) {
+    dw_add_dw(s1, e1, s2, e2);  // double-word pairs add as double-word numbers
   } else {
     A x = s1 + s2;
     A bp = x - s1;

@@ -123,8 +123,10 @@ int compute_by_mode(int mode, const void* seed, int64_t iters, const twofold_lau
       if constexpr (DOT) return launch_compute<T, T, kRigorousRounded, DOT>(seed, iters, lc, sink, st);
       return TWOFOLD_EINVAL;
     case kWide:
-      if constexpr (sizeof(T) == 4) return launch_compute<T, double, kWide, DOT>(seed, iters, lc, sink, st);
-      return TWOFOLD_EINVAL;
+      if constexpr (sizeof(T) == 4)
+        return launch_compute<T, double, kWide, DOT>(seed, iters, lc, sink, st);
+      else
+        return launch_compute<T, double, kDoubleDouble, DOT>(seed, iters, lc, sink, st);
     default: return TWOFOLD_EINVAL;
   }
 }
@@ -168,7 +170,7 @@ int twofold_probe_compute(int dtype, int is_dot, int mode, const void* seed, int
                           const twofold_launch_t* launch, double* sink, void* stream) {
   if (!seed || !sink || iters < 0 || !launch_ok(launch)) return TWOFOLD_EINVAL;
   if (dtype != 4 && dtype != 8) return TWOFOLD_EINVAL;
-  if (mode < kPlain || mode > kRigorousRounded || (mode == kWide && dtype != 4) ||
+  if (mode < kPlain || mode > kRigorousRounded ||
       ((mode == kFastRounded || mode == kRigorousRounded) && !is_dot))
     return TWOFOLD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(seed) % uintptr_t(dtype)) || (reinterpret_cast<uintptr_t>(sink) & 7u))

@@ -111,8 +111,10 @@ int seg_by_mode(int mode, const T* x, const T* y, const int64_t* off, int64_t ns
       if constexpr (DOT) TWOFOLD_SEG_MODE(T, kRigorousRounded);
       return TWOFOLD_EINVAL;
     case kWide:
-      if constexpr (sizeof(T) == 4) TWOFOLD_SEG_MODE(double, kWide);
-      return TWOFOLD_EINVAL;
+      if constexpr (sizeof(T) == 4)
+        TWOFOLD_SEG_MODE(double, kWide);
+      else
+        TWOFOLD_SEG_MODE(double, kDoubleDouble);
     default: return TWOFOLD_EINVAL;
   }
 #undef TWOFOLD_SEG_MODE
@@ -124,8 +126,9 @@ int seg_entry(const T* x, const T* y, int64_t n_total, const int64_t* off, int64
   const int dtype = int(sizeof(T));
   if ((!x && n_total > 0) || !out || !off || (DOT && !y && n_total > 0) || n_total < 0 || nseg < 0)
     return TWOFOLD_EINVAL;
-  // binary64 results (wide) go through a plan, whose output is untyped
-  if (!mode_ok(dtype, DOT, mode) || mode == kWide) return TWOFOLD_EINVAL;
+  // binary64 results of binary32 data (wide) go through a plan, whose output
+  // is untyped; for binary64 data the wide (double-word) pairs fit out
+  if (!mode_ok(dtype, DOT, mode) || (mode == kWide && dtype == 4)) return TWOFOLD_EINVAL;
   if (!elem_aligned(x, dtype) || (DOT && !elem_aligned(y, dtype)) || !elem_aligned(out, dtype) ||
       !elem_aligned(off, 8))
     return TWOFOLD_EALIGN;

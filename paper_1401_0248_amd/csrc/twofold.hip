@@ -59,8 +59,10 @@ int single_by_mode(int mode, const T* x, const T* y, int64_t n, const twofold_la
       if constexpr (DOT) return launch_single<T, T, kRigorousRounded, DOT>(x, y, n, lc, part, out, st);
       return TWOFOLD_EINVAL;
     case kWide:
-      if constexpr (sizeof(T) == 4) return launch_single<T, double, kWide, DOT>(x, y, n, lc, part, out, st);
-      return TWOFOLD_EINVAL;
+      if constexpr (sizeof(T) == 4)
+        return launch_single<T, double, kWide, DOT>(x, y, n, lc, part, out, st);
+      else
+        return launch_single<T, double, kDoubleDouble, DOT>(x, y, n, lc, part, out, st);
     default: return TWOFOLD_EINVAL;
   }
 }
@@ -112,6 +114,7 @@ int twofold_sum_f32(const float* x, int64_t n, int mode, const twofold_launch_t*
 }
 int twofold_sum_f64(const double* x, int64_t n, int mode, const twofold_launch_t* launch,
                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
+  if (mode == kWide) return TWOFOLD_EINVAL;  // the wider accumulator: twofold_sumd_f64
   return single_entry<double, false>(x, nullptr, n, mode, launch, out, ws, ws_bytes, stream);
 }
 int twofold_dot_f32(const float* x, const float* y, int64_t n, int mode,
@@ -123,6 +126,7 @@ int twofold_dot_f32(const float* x, const float* y, int64_t n, int mode,
 int twofold_dot_f64(const double* x, const double* y, int64_t n, int mode,
                     const twofold_launch_t* launch, twofold_f64_t* out, void* ws, size_t ws_bytes,
                     void* stream) {
+  if (mode == kWide) return TWOFOLD_EINVAL;  // the wider accumulator: twofold_dotd_f64
   return single_entry<double, true>(x, y, n, mode, launch, out, ws, ws_bytes, stream);
 }
 int twofold_sumd_f32(const float* x, int64_t n, const twofold_launch_t* launch, twofold_f64_t* out,
@@ -132,6 +136,14 @@ int twofold_sumd_f32(const float* x, int64_t n, const twofold_launch_t* launch, 
 int twofold_dotd_f32(const float* x, const float* y, int64_t n, const twofold_launch_t* launch,
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
   return single_entry<float, true>(x, y, n, kWide, launch, out, ws, ws_bytes, stream);
+}
+int twofold_sumd_f64(const double* x, int64_t n, const twofold_launch_t* launch,
+                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
+  return single_entry<double, false>(x, nullptr, n, kWide, launch, out, ws, ws_bytes, stream);
+}
+int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_launch_t* launch,
+                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
+  return single_entry<double, true>(x, y, n, kWide, launch, out, ws, ws_bytes, stream);
 }
 
 const char* twofold_strerror(int status) {

@@ -16,6 +16,9 @@ The tuned values change result bits (the reduction order depends on the
 launch), so the table is checked in and changed only by re-running this.
 
 Usage: python -m paper_1401_0248_amd.tune --out tuned_table.inc [--quick]
+       [--only single|seg] [--combo DTYPE,IS_DOT,MODE ...]
+With --combo only those combinations are timed, and the file holds only
+their rows, to be merged into csrc/tuned_table.inc in place of theirs.
 """
 import argparse
 import itertools
@@ -34,12 +37,13 @@ import paper_1401_0248_amd as tf  # noqa: E402
 
 MODES = {0: "plain", 1: "fast", 2: "rigorous", 3: "wide", 4: "kahan", 5: "fast_rounded",
          6: "rigorous_rounded"}
-# (dtype, is_dot, mode): every form of the library; wide is binary32 only and
-# the rounded-product forms are dots only
+# (dtype, is_dot, mode): every form of the library (wide is binary64 for
+# binary32 data and double-word for binary64 data); the rounded-product
+# forms are dots only
 COMBOS = [(4, 0, 0), (4, 0, 1), (4, 0, 2), (4, 0, 3), (4, 0, 4),
-          (8, 0, 0), (8, 0, 1), (8, 0, 2), (8, 0, 4),
+          (8, 0, 0), (8, 0, 1), (8, 0, 2), (8, 0, 3), (8, 0, 4),
           (4, 1, 0), (4, 1, 1), (4, 1, 2), (4, 1, 3), (4, 1, 4), (4, 1, 5), (4, 1, 6),
-          (8, 1, 0), (8, 1, 1), (8, 1, 2), (8, 1, 4), (8, 1, 5), (8, 1, 6)]
+          (8, 1, 0), (8, 1, 1), (8, 1, 2), (8, 1, 3), (8, 1, 4), (8, 1, 5), (8, 1, 6)]
 INT64_MAX = "INT64_MAX"
 
 
@@ -78,13 +82,13 @@ def single_candidates(quick):
     return list(itertools.product(bts, us, gbs))
 
 
-def tune_single(dev, quick):
+def tune_single(dev, quick, combos):
     rows = []
     # bucket upper bounds and the size timed for each
     buckets = [(1 << 14, 1 << 14), (1 << 18, 1 << 18), (1 << 22, 1 << 22), (1 << 25, 1 << 25),
                (INT64_MAX, None)]
     big = {4: 1 << 28, 8: 1 << 27}  # 1 GiB per vector
-    for dtype, is_dot, mode in COMBOS:
+    for dtype, is_dot, mode in combos:
         tdt = torch.float32 if dtype == 4 else torch.float64
         for n_max, n in buckets:
             n = n or big[dtype]
@@ -129,7 +133,7 @@ def tune_single(dev, quick):
     return rows
 
 
-def tune_seg(dev, quick):
+def tune_seg(dev, quick, combos):
     import synth
     rows = []
     buckets = [((1 << 24), synth.segment_lengths(3, 2000, max_len=1 << 14)),
@@ -137,7 +141,7 @@ def tune_seg(dev, quick):
                (INT64_MAX, synth.segment_lengths(3, 20000, max_len=1 << 20))]
     if quick:
         buckets = buckets[:2]
-    for dtype, is_dot, mode in COMBOS:
+    for dtype, is_dot, mode in combos:
         tdt = torch.float32 if dtype == 4 else torch.float64
         W = 16 // dtype
         for n_max, lengths in buckets:
@@ -190,15 +194,24 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--quick", action="store_true", help="fewer candidates (smoke use)")
     ap.add_argument("--only", choices=("single", "seg"), default=None)
+    ap.add_argument("--combo", action="append", default=None, metavar="DTYPE,IS_DOT,MODE",
+                    help="tune only these combinations (repeatable), e.g. 8,1,3")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
-    name = torch.cuda.get_device_name(dev)
+    props = torch.cuda.get_device_properties(dev)
+    name = "%s (%s)" % (props.name, getattr(props, "gcnArchName", "unknown arch"))
     t0 = time.time()
+    combos = COMBOS
+    if args.combo:
+        combos = [tuple(int(v) for v in c.split(",")) for c in args.combo]
+        for c in combos:
+            if c not in COMBOS:
+                ap.error("unknown combination %s" % (c,))
     rows = []
     if args.only in (None, "single"):
-        rows += tune_single(dev, args.quick)
+        rows += tune_single(dev, args.quick, combos)
     if args.only in (None, "seg"):
-        rows += tune_seg(dev, args.quick)
+        rows += tune_seg(dev, args.quick, combos)
     with open(args.out, "w") as f:
         f.write(HEADER % name)
         for r in rows:

@@ -71,7 +71,8 @@ def test_single_argument_checks():
     assert L.twofold_sum_f32(fake, -1, 2, None, fake, ws, big, None) == EINVAL
     assert L.twofold_sum_f32(fake, 10, 7, None, fake, ws, big, None) == EINVAL
     assert L.twofold_sum_f32(fake, 10, 3, None, fake, ws, big, None) == EINVAL  # wide: use sumd
-    assert L.twofold_sum_f64(fake, 10, 3, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_sum_f64(fake, 10, 3, None, fake, ws, big, None) == EINVAL  # wide: use sumd
+    assert L.twofold_dot_f64(fake, fake, 10, 3, None, fake, ws, big, None) == EINVAL
     assert L.twofold_sum_f32(fake, 10, 5, None, fake, ws, big, None) == EINVAL  # rounded: dots only
     assert L.twofold_sum_f64(fake, 10, 6, None, fake, ws, big, None) == EINVAL
     assert L.twofold_sum_f64(fake, 10, 8, None, fake, ws, big, None) == EINVAL
@@ -148,8 +149,10 @@ def test_plan_rejects_bad_offsets_before_any_hip_call():
                                          ctypes.byref(h)) == EOFFSETS
         assert not h.value
     a = np.array([0, 5], dtype=np.int64)
-    assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 8, 0, 3, None,
-                                     ctypes.byref(h)) == EINVAL  # wide needs binary32
+    assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 8, 0, 5, None,
+                                     ctypes.byref(h)) == EINVAL  # rounded forms: dots only
+    assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 8, 1, 7, None,
+                                     ctypes.byref(h)) == EINVAL  # no such mode
     assert L.twofold_seg_plan_create(None, 1, 4, 0, 2, None, ctypes.byref(h)) == EINVAL
     assert L.twofold_seg_plan_destroy(None) == 0
     assert L.twofold_seg_plan_workspace_bytes(None) == 0
@@ -163,6 +166,7 @@ def test_probe_argument_checks():
     assert L.twofold_probe_read(ctypes.c_void_p(0x10008), None, 160, ctypes.byref(lc), fake,
                                 None) == EALIGN
     assert L.twofold_probe_read(fake, None, 160, None, fake, None) == EINVAL
-    assert L.twofold_probe_compute(8, 0, 3, fake, 10, ctypes.byref(lc), fake, None) == EINVAL
+    assert L.twofold_probe_compute(8, 0, 5, fake, 10, ctypes.byref(lc), fake, None) == EINVAL
+    assert L.twofold_probe_compute(8, 1, 7, fake, 10, ctypes.byref(lc), fake, None) == EINVAL
 
 

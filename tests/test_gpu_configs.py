@@ -114,6 +114,12 @@ def test_illconditioned_bench_workload(illcond, dtype):
                 (d, mode, got)
             if mode == "rigorous":
                 assert abs(ex.diff(*got)) <= 4 * N_ILL * u * u * ex.A, (d, got)
+        if dtype == np.float64:
+            # the wide accumulator (double-word) of the same data, default launch
+            dl = tf.default_launch(0, 8, True, "wide", N_ILL)
+            got = pair(tf.dotd(xd, yd))
+            Lc, D = bounds.single_depths(dtype, N_ILL, dl.block_threads, dl.unroll, dl.grid_blocks)
+            assert abs(ex.diff(*got)) <= bounds.dw_bound(Lc, D, ex.A), (d, got)
         # the plain value of the same launch is the twofold value
         lc, _ = _bench_launch(dtype, "rigorous", N_ILL)
         assert pair(tf.dot(xd, yd, "plain", lc))[0] == pair(tf.dot(xd, yd, "rigorous", lc))[0]
@@ -146,6 +152,9 @@ def test_one_gib_dot_f64():
     lc = tf.default_launch(0, 8, True, "rigorous", n)
     assert abs(ex.diff(v, e)) <= bounds.single_bound(np.float64, n, lc.block_threads, lc.unroll,
                                                      lc.grid_blocks, ex.A)
+    dl = tf.default_launch(0, 8, True, "wide", n)
+    Lc, D = bounds.single_depths(np.float64, n, dl.block_threads, dl.unroll, dl.grid_blocks)
+    assert abs(ex.diff(*pair(tf.dotd(xd, yd)))) <= bounds.dw_bound(Lc, D, ex.A)
     lc = tf.Launch(512, 2, 256, 0, 0)
     got = pair(tf.dot(xd, yd, "rigorous", lc))
     assert same_bits(got, oracle.model_single("rigorous", x, y, mis, 512, 2, 256))

@@ -75,19 +75,28 @@ def test_seg_bound_default_launch(dtype):
         assert exs.diff(*gs[s]) == 0.0 and exs.diff(*gf[s]) == 0.0
 
 
-def test_wide_plan_vs_model():
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_wide_plan_vs_model(dtype):
     L = _lengths()
     off = synth.offsets_from_lengths(L)
-    x, y = synth.uniform(4, int(off[-1]), np.float32, count=2)
+    x, y = synth.uniform(4, int(off[-1]), dtype, count=2)
     xd, mis = to_dev(x, 1)
     yd, _ = to_dev(y, 0)
-    lc = launch(256, 4, 17, 1024)
+    W = 16 // np.dtype(dtype).itemsize
+    ts = 64 * W * 4
+    lc = launch(256, 4, 17, ts)
+    tdt = torch.float32 if dtype == np.float32 else torch.float64
+    od = torch.from_numpy(np.asarray(off, dtype=np.int64)).to(DEV)
     for is_dot in (False, True):
-        plan = tf.SegPlan(off, torch.float32, is_dot, "wide", lc)
+        plan = tf.SegPlan(off, tdt, is_dot, "wide", lc)
         got = _rows(plan.execute(xd, yd if is_dot else None))
-        want = oracle.model_seg("wide", x, off, y if is_dot else None, mis, 4, 1024)
+        want = oracle.model_seg("wide", x, off, y if is_dot else None, mis, 4, ts)
         for s in range(len(L)):
             assert same_bits(got[s], want[s]), s
+        if dtype == np.float64:  # the device-offset path takes binary64 wide too
+            dev = _rows(tf.segdot(xd, yd, od, "wide", lc) if is_dot else tf.segsum(xd, od, "wide", lc))
+            for s in range(len(L)):
+                assert same_bits(dev[s], want[s]), s
 
 
 def test_invalid_device_offsets_give_nan():

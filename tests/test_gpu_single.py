@@ -63,12 +63,16 @@ def test_rounded_product_dots_vs_model(dtype, mode):
             assert same_bits(got, want), (n, bt, u, gb, xs, ys)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("is_dot", [False, True])
-def test_wide_bitwise_vs_model(is_dot):
+def test_wide_bitwise_vs_model(dtype, is_dot):
+    """sumd/dotd: binary64 accumulation of binary32 data, double-word
+    accumulation of binary64 data."""
+    W = 16 // np.dtype(dtype).itemsize
     for n in SIZES:
-        x, y = _data(n + 2, n, np.float32)
+        x, y = _data(n + 2, n, dtype)
         for bt, u, gb in LAUNCHES[:4]:
-            xd, mis = to_dev(x, n % 4)
+            xd, mis = to_dev(x, n % W)
             yd, _ = to_dev(y, 0)
             lc = launch(bt, u, gb)
             got = pair(tf.dotd(xd, yd, lc) if is_dot else tf.sumd(xd, lc))

@@ -218,7 +218,7 @@ def test_model_rejects_bad_arguments():
     with pytest.raises(ValueError):
         oracle.model_single("rigorous", x, None, 0, 100, 1, 1)
     with pytest.raises(ValueError):
-        oracle.model_single("wide", x, None, 0, 256, 1, 1)
+        oracle.model_single(9, x, None, 0, 256, 1, 1)
     with pytest.raises(ValueError):
         oracle.model_single("fast_rounded", x, None, 0, 256, 1, 1)
     with pytest.raises(ValueError):
@@ -327,3 +327,79 @@ def test_tree_bound_depths():
     assert Lc == -(-(4096 + 1) // 1024) + 2
     # a segment of three tiles: 3 + 6 inside the tile, 1 + 6 across tiles
     assert bounds.segment_depths(np.float32, 3 * 1024, 1024) == (-(-257 // 64) + 2, 3 + 6 + 1 + 6)
+
+
+# ---- the wide accumulator (sumd/dotd): binary64 for binary32 data, double-
+# ---- word for binary64 data ---------------------------------------------------
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("is_dot", [False, True])
+def test_wide_single_lane_reduces_to_sequential(dtype, is_dot):
+    """Data on one lane's chain: the model equals the sequential wide loop
+    (sumd/dotd for binary32 data; the double-word sumdd/dotdd for binary64)."""
+    W = 16 // np.dtype(dtype).itemsize
+    bt, U, gb = 128, 2, 3
+    L = bt * gb
+    rng = np.random.default_rng(22)
+    nvec = 11 * U * L + 7
+    n = nvec * W
+    idx = list(range(0, nvec, L))
+    idx = [k * W for k in idx]
+    x = np.zeros(n, dtype=dtype)
+    vals = (rng.standard_normal(len(idx)) * np.exp2(rng.integers(-30, 30, len(idx)))).astype(dtype)
+    x[idx] = vals
+    y = rng.standard_normal(n).astype(dtype) if is_dot else None
+    yv = y[idx] if is_dot else None
+    got = oracle.model_single("wide", x, y, 0, bt, U, gb)
+    if dtype == np.float64:
+        v, e = oracle.seq("dotdd" if is_dot else "sumdd", vals, yv)
+    else:
+        v, e = oracle.seq("dotd" if is_dot else "sumd", vals, yv)
+    assert got[0] == float(v) and got[1] == float(e)
+
+
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_double_word_within_bound(launch):
+    """Binary64 wide results lie within the double-word bound of their tree
+    and are normalized double-word numbers."""
+    bt, U, gb = launch
+    n = 1 << 14
+    for name, x, y in _datasets(np.float64, n, 7):
+        for yy in (None, y):
+            ex = oracle.Exact(x, yy)
+            got = oracle.model_single("wide", x, yy, 0, bt, U, gb)
+            Lc, D = bounds.single_depths(np.float64, n, bt, U, gb)
+            assert abs(ex.diff(got[0], got[1])) <= bounds.dw_bound(Lc, D, ex.A), (name, yy is None)
+            assert got[0] == got[0] + got[1]  # normalized double-word result
+
+
+def test_sequential_double_word_pinned_by_fractions():
+    """The sequential double-word dot on small inputs: error at most
+    (3u^2 + 13u^3) times the sum of the exact partial results' magnitudes."""
+    u = 2.0 ** -53
+    rng = np.random.default_rng(23)
+    for trial in range(40):
+        n = int(rng.integers(2, 200))
+        x = rng.standard_normal(n) * np.exp2(rng.integers(-20, 20, n))
+        y = rng.standard_normal(n) * np.exp2(rng.integers(-20, 20, n))
+        if trial % 2:
+            y[n // 2:] = -x[:n - n // 2] * y[:n - n // 2] / np.where(x[n // 2:] == 0, 1, x[n // 2:])
+        v, e = oracle.seq("dotdd", x, y)
+        part, tot = F(0), F(0)
+        for a, b in zip(x, y):
+            part += F(float(a)) * F(float(b))
+            tot += abs(part)
+        err = abs(F(float(v)) + F(float(e)) - part)
+        assert err <= (F(3 * u * u) + 13 * F(u) ** 3) * tot * (1 + F(1, 1 << 20))
+
+
+def test_double_word_segments_within_bound():
+    ts = 64 * 2 * 4
+    lengths = synth.segment_lengths(5, 80, max_len=1 << 14)
+    off = synth.offsets_from_lengths(lengths)
+    x, y = synth.illcond_dot(synth.illcond_seed(12), int(off[-1]), 1e12, np.float64)
+    got = oracle.model_seg("wide", x, off, y, 0, 4, ts)
+    for s in range(len(lengths)):
+        a, b = off[s], off[s + 1]
+        ex = oracle.Exact(x[a:b], y[a:b])
+        Lc, D = bounds.segment_depths(np.float64, b - a, ts)
+        assert abs(ex.diff(*got[s])) <= bounds.dw_bound(Lc, D, ex.A), s

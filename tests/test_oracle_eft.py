@@ -163,3 +163,58 @@ def test_random_pairs_python_floats():
         b = rnd.uniform(-1, 1) * 2.0 ** rnd.randint(-60, 60)
         v, e = oracle.seq("sumt", np.array([a, b]))
         assert F(v) + F(e) == F(a) + F(b)
+
+
+# ---- double-word additions (the wide accumulator for binary64 data) ----------
+def _dw(rng, scale):
+    """A random normalized double-word number (h, l), h = fl(h + l)."""
+    h = float(rng.standard_normal() * 2.0 ** scale)
+    l = float(rng.standard_normal()) * abs(h) * 2.0 ** -int(rng.integers(53, 60))
+    hh, ll = oracle.dw_plus_fp(h, 0.0, l)  # renormalize
+    return hh, ll
+
+
+def test_dw_additions_within_published_bounds():
+    """DWPlusFP within 2u^2 and AccurateDWPlusDW within 3u^2 + 13u^3 of the
+    exact sum (Joldes, Muller, Popescu 2017, Algorithms 4 and 6), results
+    normalized, on random pairs with cancellations and wide exponent gaps."""
+    u = 2.0 ** -53
+    rng = np.random.default_rng(31)
+    for _ in range(4000):
+        xh, xl = _dw(rng, int(rng.integers(-30, 30)))
+        yh, yl = _dw(rng, int(rng.integers(-30, 30)))
+        if rng.random() < 0.3:  # heavy cancellation
+            yh, yl = oracle.dw_plus_fp(-xh, 0.0, xh * 2.0 ** -int(rng.integers(20, 60)))
+        exact = F(xh) + F(xl) + F(yh) + F(yl)
+        zh, zl = oracle.dw_plus_dw(xh, xl, yh, yl)
+        assert zh == zh + zl
+        assert abs(F(zh) + F(zl) - exact) <= (F(3 * u * u) + F(13) * F(u) ** 3) * abs(exact)
+        y = float(yh)
+        exact = F(xh) + F(xl) + F(y)
+        zh, zl = oracle.dw_plus_fp(xh, xl, y)
+        assert zh == zh + zl
+        assert abs(F(zh) + F(zl) - exact) <= 2 * F(u) * F(u) * abs(exact)
+
+
+def test_dw_step_catches_a_dropped_term():
+    """The pins are sharp enough to see a mistake: dropping the low parts'
+    two-sum remainder (tl) breaks the bound on some input."""
+    u = 2.0 ** -53
+    rng = np.random.default_rng(32)
+    bad = 0
+    for _ in range(2000):
+        xh, xl = _dw(rng, 0)
+        yh, yl = _dw(rng, 0)
+        exact = F(xh) + F(xl) + F(yh) + F(yl)
+        sh = xh + yh
+        bv = sh - xh
+        sl = (xh - (sh - bv)) + (yh - bv)
+        th = xl + yl  # the two-sum remainder of the low parts is dropped
+        c = sl + th
+        vh = sh + c
+        vl = c - (vh - sh)
+        zh = vh + vl
+        zl = vl - (zh - vh)
+        if abs(F(zh) + F(zl) - exact) > (F(3 * u * u) + F(13) * F(u) ** 3) * abs(exact):
+            bad += 1
+    assert bad > 0
