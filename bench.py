@@ -88,7 +88,7 @@ def exact_timing(oracle, x, y):
     return res
 
 
-def oracle_leg(host, gpu, launches):
+def oracle_leg(host, gpu, launches, perm_host=None, perm_gpu=None):
     """The CPU-baseline leg, the only part of the benchmark that runs the
     oracle: (1) times the oracle's sequential rigorous and fast twofold dots
     (paper order, FMA remainder) over every input of one step on one host
@@ -139,6 +139,18 @@ def oracle_leg(host, gpu, launches):
         else:
             rows.setdefault("f64_double_word", []).append(abs(ex.diff(p[0], p[1])) / ex.A)
         rows.setdefault("cond_" + key, []).append(2 * ex.A / abs(ex.S) if ex.S else float("inf"))
+    if perm_host:
+        pr = {"measure": "|v + e - S| / sum|x y| on the target-cond-1e16 pairs under a seeded "
+                         "permutation (running sums no longer cancel in order)"}
+        for dt, (x, y) in perm_host.items():
+            ex = oracle.Exact(x, y)
+            key = "f32" if dt == np.float32 else "f64"
+            for mode in ("plain", "fast", "rigorous"):
+                p = perm_gpu[(dt, mode)]
+                pr["%s_%s" % (key, mode)] = float("%.3g" % (abs(ex.diff(p[0], p[1])) / ex.A))
+            p = perm_gpu[(dt, "dotd")]
+            pr["f32data_f64plain" if dt == np.float32 else "f64_double_word"] = float(
+                "%.3g" % (abs(ex.diff(p[0], p[1])) / ex.A))
     acc = {"measure": "median over conditions of |v + e - S| / sum|x y| (*_value: |v - S| / "
                       "sum|x y|; *_q: e / (S - v); *_over_tree_bound: the largest |v + e - S| "
                       "over the proven bound of the launch's reduction tree)"}
@@ -149,6 +161,8 @@ def oracle_leg(host, gpu, launches):
             acc[k] = float("%.3g" % max(v))
         else:
             acc[k] = float("%.3g" % np.median(v))
+    if perm_host:
+        acc["permuted"] = pr
     return base, acc
 
 
@@ -578,7 +592,16 @@ def main():
         log("cpu baseline leg: oracle timing and grading")
         launches = {(dt, m): tf.default_launch(0, np.dtype(dt).itemsize, True, m, N)
                     for dt in (np.float32, np.float64) for m in ("rigorous", "fast")}
-        res["cpu_baseline"], res["accuracy"] = oracle_leg(host, gpu, launches)
+        import synth
+        perm_host, perm_gpu = {}, {}
+        for dt in (np.float32, np.float64):
+            px, py = synth.permute_pairs(synth.illcond_perm_seed(16), *host[(dt, 16)])
+            perm_host[dt] = (px, py)
+            xd, yd = torch.from_numpy(px).to(dev), torch.from_numpy(py).to(dev)
+            for mode in ("plain", "fast", "rigorous"):
+                perm_gpu[(dt, mode)] = tf.dot(xd, yd, mode).double().cpu().numpy()
+            perm_gpu[(dt, "dotd")] = tf.dotd(xd, yd).cpu().numpy()
+        res["cpu_baseline"], res["accuracy"] = oracle_leg(host, gpu, launches, perm_host, perm_gpu)
     print(json.dumps(res), flush=True)
 
 

@@ -181,6 +181,20 @@ def illcond_seed(decade):
     return (4, int(decade))
 
 
+def illcond_perm_seed(decade):
+    """Seed of the permutation applied to those inputs (permuted variant)."""
+    return (4, int(decade), 1)
+
+
+def permute_pairs(seed, x, y):
+    """x and y reordered by one seeded permutation: positions sorted by n
+    raw 64-bit draws (stable sort, so ties, if any, keep index order). The
+    multiset of products x_i*y_i, hence the exact dot and its condition, is
+    unchanged; the running sums no longer cancel in order."""
+    order = np.argsort(raw(_rng(seed), x.size), kind="stable")
+    return np.ascontiguousarray(x[order]), np.ascontiguousarray(y[order])
+
+
 def segment_lengths(seed, nseg, max_len=1 << 20):
     """nseg lengths log-uniform in [1, max_len]:
     L = max(1, floor(exp(u * ln(max_len)))) with u uniform in [0, 1)."""

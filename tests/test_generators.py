@@ -65,3 +65,16 @@ def test_illcond_reaches_its_decade(dtype):
 def test_hundred_hours_input():
     x = synth.hundred_hours()
     assert x.size == 3_600_000 and x.dtype == np.float32 and np.all(x == np.float32(0.1))
+
+
+def test_permuted_illcond_keeps_the_exact_dot():
+    import oracle
+    for dtype in (np.float32, np.float64):
+        x, y = synth.illcond_dot(synth.illcond_seed(12), 1 << 12, 1e12, dtype)
+        px, py = synth.permute_pairs(synth.illcond_perm_seed(12), x, y)
+        qx, qy = synth.permute_pairs(synth.illcond_perm_seed(12), x, y)
+        assert np.array_equal(px, qx) and np.array_equal(py, qy)  # reproducible
+        assert not np.array_equal(px, x)
+        assert sorted((x.astype(np.float64) * y).tolist()) == sorted((px.astype(np.float64) * py).tolist())
+        a, b = oracle.Exact(x, y), oracle.Exact(px, py)
+        assert a.S == b.S and a.diff(a.S) == b.diff(a.S) and a.A == b.A

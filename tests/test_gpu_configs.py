@@ -287,3 +287,31 @@ def test_beyond_2e31_elements():
     plan.close()
     del xd
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_permuted_illconditioned(dtype):
+    """The permuted variant of the ill-conditioned dot (cond 1e16, N = 2^20):
+    the running sums no longer cancel in order. Rigorous, fast and wide
+    results equal the order model's and lie within their tree bounds."""
+    n = 1 << 20
+    x, y = synth.illcond_dot(synth.illcond_seed(16), n, 1e16, dtype)
+    x, y = synth.permute_pairs(synth.illcond_perm_seed(16), x, y)
+    _note("permuted ill-conditioned %s" % np.dtype(dtype).name)
+    xd, mis = to_dev(x)
+    yd, _ = to_dev(y)
+    ex = oracle.Exact(x, y)
+    bt, un, gb = 256, 4, 128
+    lc = tf.Launch(bt, un, gb, 0, 0)
+    for mode in ("rigorous", "fast"):
+        got = pair(tf.dot(xd, yd, mode, lc))
+        want, sv = oracle.model_single(mode, x, y, mis, bt, un, gb, with_violations=True)
+        assert same_bits(got, want), mode
+        assert abs(ex.diff(*got)) <= bounds.single_bound(dtype, n, bt, un, gb, ex.A, sv), mode
+    got = pair(tf.dotd(xd, yd, lc))
+    assert same_bits(got, oracle.model_single("wide", x, y, mis, bt, un, gb))
+    if dtype == np.float64:
+        Lc, D = bounds.single_depths(dtype, n, bt, un, gb)
+        assert abs(ex.diff(*got)) <= bounds.dw_bound(Lc, D, ex.A)
+    else:
+        assert abs(ex.diff(got[0])) <= n * 2.0 ** -53 * ex.A
