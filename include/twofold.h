@@ -111,6 +111,7 @@
  * Status: 0 on success, a negative TWOFOLD_E* code otherwise; arguments are
  * checked on the host before any HIP call, and nothing is launched on
  * error. Non-finite inputs give IEEE values and an unspecified error.
+ * Element counts (n, n_total, nseg, offsets[nseg]) are at most 2^56.
  */
 #ifndef TWOFOLD_H
 #define TWOFOLD_H

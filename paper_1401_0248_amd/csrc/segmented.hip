@@ -124,7 +124,8 @@ template <typename T, bool DOT>
 int seg_entry(const T* x, const T* y, int64_t n_total, const int64_t* off, int64_t nseg, int mode,
               const twofold_launch_t* launch, void* out, void* ws, size_t ws_bytes, void* stream) {
   const int dtype = int(sizeof(T));
-  if ((!x && n_total > 0) || !out || !off || (DOT && !y && n_total > 0) || n_total < 0 || nseg < 0)
+  if ((!x && n_total > 0) || !out || !off || (DOT && !y && n_total > 0) || !valid_count(n_total) ||
+      !valid_count(nseg))
     return TWOFOLD_EINVAL;
   // binary64 results of binary32 data (wide) go through a plan, whose output
   // is untyped; for binary64 data the wide (double-word) pairs fit out
@@ -190,7 +191,9 @@ extern "C" {
 
 size_t twofold_workspace_bytes_seg(int dtype, int is_dot, int mode, int64_t n_total, int64_t nseg,
                                    const twofold_launch_t* launch) {
-  if (!valid_dtype(dtype) || n_total < 0 || nseg < 0 || !mode_ok(dtype, is_dot != 0, mode)) return 0;
+  if (!valid_dtype(dtype) || !valid_count(n_total) || !valid_count(nseg) ||
+      !mode_ok(dtype, is_dot != 0, mode))
+    return 0;
   twofold_launch_t lc;
   if (resolve_seg(dtype, is_dot != 0, mode, n_total, launch, &lc)) return 0;
   return seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems)).total;
@@ -223,12 +226,13 @@ int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype
                             int mode, const twofold_launch_t* launch, twofold_seg_plan_t** plan) {
   if (!plan) return TWOFOLD_EINVAL;
   *plan = nullptr;
-  if (!offsets_host || nseg < 0 || !valid_dtype(dtype)) return TWOFOLD_EINVAL;
+  if (!offsets_host || !valid_count(nseg) || !valid_dtype(dtype)) return TWOFOLD_EINVAL;
   if (!mode_ok(dtype, is_dot != 0, mode)) return TWOFOLD_EINVAL;
   if (offsets_host[0] != 0) return TWOFOLD_EOFFSETS;
   for (int64_t s = 0; s < nseg; s++)
     if (offsets_host[s + 1] < offsets_host[s]) return TWOFOLD_EOFFSETS;
   const int64_t n_total = offsets_host[nseg];
+  if (!valid_count(n_total)) return TWOFOLD_EINVAL;
   twofold_launch_t lc;
   const int rc = resolve_seg(dtype, is_dot != 0, mode, n_total, launch, &lc);
   if (rc) return rc;

@@ -74,7 +74,7 @@ int single_entry(const T* x, const T* y, int64_t n, int mode, const twofold_laun
   const int dtype = int(sizeof(T));
   // Data pointers may be NULL only when there is no data (torch hands out
   // NULL for empty tensors).
-  if ((!x && n > 0) || !out || (DOT && !y && n > 0) || n < 0) return TWOFOLD_EINVAL;
+  if ((!x && n > 0) || !out || (DOT && !y && n > 0) || !valid_count(n)) return TWOFOLD_EINVAL;
   if (!mode_ok(dtype, DOT, mode)) return TWOFOLD_EINVAL;
   if (!elem_aligned(x, dtype) || (DOT && !elem_aligned(y, dtype))) return TWOFOLD_EALIGN;
   if (!elem_aligned(out, out_f64(dtype, mode) ? 8 : 4)) return TWOFOLD_EALIGN;
@@ -92,7 +92,8 @@ extern "C" {
 
 int twofold_default_launch(int kind, int dtype, int is_dot, int mode, int64_t n, int64_t nseg,
                            twofold_launch_t* out) {
-  if (!out || !valid_dtype(dtype) || (kind != 0 && kind != 1) || n < 0 || nseg < 0)
+  if (!out || !valid_dtype(dtype) || (kind != 0 && kind != 1) || !valid_count(n) ||
+      !valid_count(nseg))
     return TWOFOLD_EINVAL;
   if (!mode_ok(dtype, is_dot != 0, mode)) return TWOFOLD_EINVAL;
   if (kind == 0) return resolve_single(dtype, is_dot != 0, mode, n, nullptr, out);
@@ -101,7 +102,7 @@ int twofold_default_launch(int kind, int dtype, int is_dot, int mode, int64_t n,
 
 size_t twofold_workspace_bytes_single(int dtype, int is_dot, int mode, int64_t n,
                                       const twofold_launch_t* launch) {
-  if (!valid_dtype(dtype) || n < 0 || !mode_ok(dtype, is_dot != 0, mode)) return 0;
+  if (!valid_dtype(dtype) || !valid_count(n) || !mode_ok(dtype, is_dot != 0, mode)) return 0;
   twofold_launch_t lc;
   if (resolve_single(dtype, is_dot != 0, mode, n, launch, &lc)) return 0;
   return single_ws_bytes(lc);

@@ -79,6 +79,10 @@ def test_single_argument_checks():
     assert L.twofold_workspace_bytes_single(4, 0, 5, 100, None) == 0
     assert L.twofold_workspace_bytes_single(4, 1, 5, 100, None) > 0
     assert L.twofold_dot_f64(fake, None, 10, 2, None, fake, ws, big, None) == EINVAL
+    # counts beyond 2^56
+    assert L.twofold_sum_f32(fake, (1 << 56) + 1, 2, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_workspace_bytes_single(4, 0, 2, (1 << 63) - 1, None) == 0
+    assert L.twofold_default_launch(0, 8, 1, 2, (1 << 63) - 1, 0, ctypes.byref(Launch())) == EINVAL
     # misaligned data
     assert L.twofold_sum_f64(ctypes.c_void_p(0x10004), 10, 2, None, fake, ws, big, None) == EALIGN
     assert L.twofold_dot_f32(fake, ctypes.c_void_p(0x10002), 10, 2, None, fake, ws, big, None) == EALIGN
@@ -154,6 +158,10 @@ def test_plan_rejects_bad_offsets_before_any_hip_call():
     assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 8, 1, 7, None,
                                      ctypes.byref(h)) == EINVAL  # no such mode
     assert L.twofold_seg_plan_create(None, 1, 4, 0, 2, None, ctypes.byref(h)) == EINVAL
+    a = np.array([0, 1 << 60], dtype=np.int64)
+    assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 4, 0, 2, None,
+                                     ctypes.byref(h)) == EINVAL  # beyond 2^56 elements
+    assert L.twofold_workspace_bytes_seg(4, 1, 2, 1 << 60, 10, None) == 0
     assert L.twofold_seg_plan_destroy(None) == 0
     assert L.twofold_seg_plan_workspace_bytes(None) == 0
 
