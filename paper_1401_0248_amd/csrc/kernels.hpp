@@ -89,11 +89,23 @@ __device__ __forceinline__ int64_t head_count(const T* p, int64_t len) {
 
 // Steps 1-4 of the documented order for one lane g of L lanes over the
 // range [x, x + len): head, rounds of U vectors, tail, chain merge.
+//
+// The head and tail elements are requested first. With at most four
+// vectors per round (U = 1, 2, 4 for a sum, U = 1, 2 for a dot) the loads
+// also run one round ahead of the arithmetic: round 0 is requested with the
+// head and tail, and while the steps of round q run, the loads of round
+// q + 1 (or of the last, partial round) are in flight. Wider rounds already
+// keep enough bytes in flight per lane and would not fit two rounds in the
+// 128 registers of a 1024-thread block, so they load each round when it
+// starts. Either way the steps are applied in the documented order (head,
+// rounds in order, partial round, tail), so the result does not depend on
+// when the data arrived.
 template <typename T, typename A, int M, bool DOT, bool YV, int U>
 __device__ __forceinline__ void lane_reduce(const T* __restrict__ x, const T* __restrict__ y,
                                             int64_t len, int64_t head, int64_t L, int64_t g,
                                             A& s_out, A& e_out) {
   constexpr int W = 16 / static_cast<int>(sizeof(T));
+  constexpr bool kAhead = U * (DOT ? 2 : 1) <= 4;
   using V = typename vec16<T>::type;
   A cs[W], ce[W];
 #pragma unroll
@@ -101,45 +113,84 @@ __device__ __forceinline__ void lane_reduce(const T* __restrict__ x, const T* __
     cs[j] = A(0);
     ce[j] = A(0);
   }
-  if (g < head) step<M, DOT>(cs[0], ce[0], load_nt(x + g), DOT ? load_nt(y + g) : T(0));
   const T* __restrict__ xb = x + head;
   const T* __restrict__ yb = DOT ? y + head : nullptr;
   const int64_t nv = (len - head) / W;
+  const int64_t tail0 = nv * W;
+  const bool has_head = g < head;
+  const bool has_tail = g < (len - head) - tail0;
+  T hx = T(0), hy = T(0), tx = T(0), ty = T(0);
+  if (has_head) {
+    hx = load_nt(x + g);
+    if constexpr (DOT) hy = load_nt(y + g);
+  }
+  if (has_tail) {
+    tx = load_nt(xb + tail0 + g);
+    if constexpr (DOT) ty = load_nt(yb + tail0 + g);
+  }
   const int64_t per_round = static_cast<int64_t>(U) * L;
   const int64_t full = nv / per_round;
-  int64_t k0 = g;
-  for (int64_t q = 0; q < full; q++, k0 += per_round) {
-    V a[U], b[U];
+  // Round loads: all U vectors (full round) or those below nv (last round).
+  auto load_round = [&](V (&a)[U], V (&b)[U], int64_t k, bool whole) {
+    if (whole) {
 #pragma unroll
-    for (int u = 0; u < U; u++) a[u] = load_vec<T, true>(xb, k0 + u * L);
-    if constexpr (DOT) {
+      for (int u = 0; u < U; u++) a[u] = load_vec<T, true>(xb, k + u * L);
+      if constexpr (DOT) {
 #pragma unroll
-      for (int u = 0; u < U; u++) b[u] = load_vec<T, YV>(yb, k0 + u * L);
+        for (int u = 0; u < U; u++) b[u] = load_vec<T, YV>(yb, k + u * L);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        if (k + u * L < nv) {
+          a[u] = load_vec<T, true>(xb, k + u * L);
+          if constexpr (DOT) b[u] = load_vec<T, YV>(yb, k + u * L);
+        }
+      }
     }
+  };
+  // Round steps, u in order: all U vectors (full round) or those below nv
+  // (last round).
+  auto step_round = [&](const V (&a)[U], const V (&b)[U], int64_t k, bool whole) {
 #pragma unroll
     for (int u = 0; u < U; u++) {
+      if (whole || k + u * L < nv) {
 #pragma unroll
-      for (int j = 0; j < W; j++)
-        step<M, DOT>(cs[j], ce[j], vget<T>(a[u], j), DOT ? vget<T>(b[u], j) : T(0));
+        for (int j = 0; j < W; j++)
+          step<M, DOT>(cs[j], ce[j], vget<T>(a[u], j), DOT ? vget<T>(b[u], j) : T(0));
+      }
     }
-  }
-  // Last, partial round: vectors k0 + u*L below nv, u in order.
+  };
+  int64_t k0 = g;
+  if constexpr (kAhead) {
+    V a[U], b[U];  // the round whose steps run next
+    load_round(a, b, k0, full > 0);
+    if (has_head) step<M, DOT>(cs[0], ce[0], hx, hy);
+    for (int64_t q = 0; q < full; q++) {
+      const int64_t kn = k0 + per_round;
+      V na[U], nb[U];
+      load_round(na, nb, kn, q + 1 < full);
+      step_round(a, b, k0, true);
 #pragma unroll
-  for (int u = 0; u < U; u++) {
-    const int64_t k = k0 + u * L;
-    if (k < nv) {
-      V a = load_vec<T, true>(xb, k);
-      V b = a;
-      if constexpr (DOT) b = load_vec<T, YV>(yb, k);
-#pragma unroll
-      for (int j = 0; j < W; j++)
-        step<M, DOT>(cs[j], ce[j], vget<T>(a, j), DOT ? vget<T>(b, j) : T(0));
+      for (int u = 0; u < U; u++) {
+        a[u] = na[u];
+        if constexpr (DOT) b[u] = nb[u];
+      }
+      k0 = kn;
     }
+    step_round(a, b, k0, false);  // last, partial round
+  } else {
+    if (has_head) step<M, DOT>(cs[0], ce[0], hx, hy);
+    for (int64_t q = 0; q < full; q++, k0 += per_round) {
+      V a[U], b[U];
+      load_round(a, b, k0, true);
+      step_round(a, b, k0, true);
+    }
+    V a[U], b[U];
+    load_round(a, b, k0, false);
+    step_round(a, b, k0, false);  // last, partial round
   }
-  const int64_t tail0 = nv * W;
-  if (g < (len - head) - tail0) {
-    step<M, DOT>(cs[0], ce[0], load_nt(xb + tail0 + g), DOT ? load_nt(yb + tail0 + g) : T(0));
-  }
+  if (has_tail) step<M, DOT>(cs[0], ce[0], tx, ty);
   A s = cs[0], e = ce[0];
 #pragma unroll
   for (int j = 1; j < W; j++) combine<M>(s, e, cs[j], ce[j]);

@@ -85,8 +85,8 @@ def single_candidates(quick):
 def tune_single(dev, quick, combos):
     rows = []
     # bucket upper bounds and the size timed for each
-    buckets = [(1 << 14, 1 << 14), (1 << 18, 1 << 18), (1 << 22, 1 << 22), (1 << 25, 1 << 25),
-               (INT64_MAX, None)]
+    buckets = [(1 << 14, 1 << 14), (1 << 18, 1 << 18), (1 << 22, 1 << 22), (1 << 24, 1 << 24),
+               (1 << 25, 1 << 25), (INT64_MAX, None)]
     big = {4: 1 << 28, 8: 1 << 27}  # 1 GiB per vector
     for dtype, is_dot, mode in combos:
         tdt = torch.float32 if dtype == 4 else torch.float64
@@ -199,7 +199,7 @@ def main():
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     props = torch.cuda.get_device_properties(dev)
-    name = "%s (%s)" % (props.name, getattr(props, "gcnArchName", "unknown arch"))
+    name = "a %s GPU" % getattr(props, "gcnArchName", props.name)
     t0 = time.time()
     combos = COMBOS
     if args.combo:
