@@ -207,7 +207,8 @@ def precision_study(torch, tf, dev, with_oracle):
                      "gelem_s": round(n / t / 1e9, 1), "gb_s": round(nbytes / t / 1e9, 1),
                      "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4)})
         log("  %-30s %8.2f us %7.1f Gelem/s" % (name, t * 1e6, n / t / 1e9))
-    res = {"workload": "precision form: binary32 twofold vs binary64 plain, N=2^26, "
+    res = {"device": device_info(torch, dev),
+           "workload": "precision form: binary32 twofold vs binary64 plain, N=2^26, "
                        "x, y = uniform(-1,1) * 2^k, k in [-20, 20], seed 2",
            "n": n, "rows": rows}
     if with_oracle:
@@ -230,6 +231,13 @@ def precision_study(torch, tf, dev, with_oracle):
 
 COPY_BYTES = 1 << 28
 FORMS = ("plain", "fast", "rigorous")
+
+
+def device_info(torch, dev):
+    """Name, architecture, compute units and memory of the device."""
+    p = torch.cuda.get_device_properties(dev)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", ""),
+            "compute_units": p.multi_processor_count, "memory_gib": round(p.total_memory / 2 ** 30, 1)}
 
 
 def graph_time(torch, calls, reps=30):
@@ -350,7 +358,8 @@ def roofline_sweep(torch, tf, dev):
                     log("  %s %-16s %10.2f us %8.1f GB/s" % (op, form, t * 1e6, nbytes / t / 1e9))
             del both, x, y
             torch.cuda.empty_cache()
-    print(json.dumps({"workload": "roofline sweep, uniform(-1,1) seed 1, tuned default launches; "
+    print(json.dumps({"device": device_info(torch, dev),
+                      "workload": "roofline sweep, uniform(-1,1) seed 1, tuned default launches; "
                                   "us = median over 30 graph replays of 50 calls (4 at 1 GiB) "
                                   "per call, warm; us_cold = one call after a 512 MiB scrub",
                       "peak_gb_s": HBM_PEAK_GBS, "rows": rows}), flush=True)
@@ -358,51 +367,56 @@ def roofline_sweep(torch, tf, dev):
 
 def segmented_batch(torch, tf, dev):
     """20,000 segment pairs with log-uniform lengths in [1, 2^20] (seed 3,
-    1,504,333,896 elements), uniform(-1, 1) data of seed 3 (x, then y),
+    1,504,333,896 elements), and the secondary variant capped at 2^17
+    (221,217,512 elements); uniform(-1, 1) data of seed 3 (x, then y),
     binary32 and binary64, fast and rigorous dots through plans with the
     tuned default launch, HIP-graph replay. One JSON line."""
     import numpy as np
     import synth
 
-    lengths = synth.segment_lengths(3, 20000)
-    off = synth.offsets_from_lengths(lengths)
-    n = int(off[-1])
     rows = []
     for dtype, tdt in ((np.float32, torch.float32), (np.float64, torch.float64)):
-        log("segmented %s: generating %d x 2 values" % (np.dtype(dtype).name, n))
-        both = to_device_chunks(torch, synth.uniform_chunks(3, 2 * n, dtype), 2 * n, tdt, dev)
-        x, y = both[:n], both[n:]
-        for form in ("fast", "rigorous"):
-            plan = tf.SegPlan(off, tdt, True, form)
-            out = torch.empty((plan.nseg, 2), dtype=plan.out_dtype, device=dev)
-            ws = tf.Workspace(plan.workspace_bytes, dev)
-            t, tmin = graph_time(torch, lambda: (plan.execute(x, y, out=out, ws=ws), 1)[1], reps=10)
-            first = out.clone()
-            plan.execute(x, y, out=out, ws=ws)
-            same = bool(torch.equal(first.view(torch.int8), out.view(torch.int8)))
-            nbytes = 2 * n * np.dtype(dtype).itemsize
-            rows.append({"dtype": np.dtype(dtype).name, "form": form, "nseg": int(plan.nseg),
-                         "elements": n, "ms": round(t * 1e3, 4), "ms_min": round(tmin * 1e3, 4),
-                         "bitwise_repeatable": same, "gelem_s": round(n / t / 1e9, 1),
-                         "gb_s": round(nbytes / t / 1e9, 1),
-                         "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
-                         "launch": plan.launch.as_dict()})
-            log("  %s %s %.3f ms %.1f GB/s" % (np.dtype(dtype).name, form, t * 1e3, nbytes / t / 1e9))
-            if form == "rigorous":
-                # the precision monitor over the batch's results (tau = 2^-20)
-                od = torch.from_numpy(np.asarray(off, dtype=np.int64)).to(dev)
-                fl = torch.empty(plan.nseg, dtype=torch.int32, device=dev)
-                nf = torch.empty((), dtype=torch.int64, device=dev)
-                tm, _ = graph_time(torch, lambda: (tf.monitor(out, 2.0 ** -20, offsets=od, flags=fl,
-                                                              nflagged=nf), 1)[1])
-                rows[-1]["monitor_us"] = round(tm * 1e6, 2)
-                rows[-1]["monitor_flagged"] = int(nf.item())
-            plan.close()
-        del both, x, y
-        torch.cuda.empty_cache()
+        for cap in (1 << 20, 1 << 17):
+            lengths = synth.segment_lengths(3, 20000, max_len=cap)
+            off = synth.offsets_from_lengths(lengths)
+            n = int(off[-1])
+            log("segmented %s, lengths up to 2^%d: generating %d x 2 values"
+                % (np.dtype(dtype).name, cap.bit_length() - 1, n))
+            both = to_device_chunks(torch, synth.uniform_chunks(3, 2 * n, dtype), 2 * n, tdt, dev)
+            x, y = both[:n], both[n:]
+            for form in ("fast", "rigorous"):
+                plan = tf.SegPlan(off, tdt, True, form)
+                out = torch.empty((plan.nseg, 2), dtype=plan.out_dtype, device=dev)
+                ws = tf.Workspace(plan.workspace_bytes, dev)
+                t, tmin = graph_time(torch, lambda: (plan.execute(x, y, out=out, ws=ws), 1)[1])
+                first = out.clone()
+                plan.execute(x, y, out=out, ws=ws)
+                same = bool(torch.equal(first.view(torch.int8), out.view(torch.int8)))
+                nbytes = 2 * n * np.dtype(dtype).itemsize
+                rows.append({"dtype": np.dtype(dtype).name, "form": form, "max_len": cap,
+                             "nseg": int(plan.nseg), "elements": n, "ms": round(t * 1e3, 4),
+                             "ms_min": round(tmin * 1e3, 4), "bitwise_repeatable": same,
+                             "gelem_s": round(n / t / 1e9, 1), "gb_s": round(nbytes / t / 1e9, 1),
+                             "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
+                             "launch": plan.launch.as_dict()})
+                log("  %s %s %.3f ms %.1f GB/s" % (np.dtype(dtype).name, form, t * 1e3,
+                                                   nbytes / t / 1e9))
+                if form == "rigorous" and cap == 1 << 20:
+                    # the precision monitor over the batch's results (tau = 2^-20)
+                    od = torch.from_numpy(np.asarray(off, dtype=np.int64)).to(dev)
+                    fl = torch.empty(plan.nseg, dtype=torch.int32, device=dev)
+                    nf = torch.empty((), dtype=torch.int64, device=dev)
+                    tm, _ = graph_time(torch, lambda: (tf.monitor(out, 2.0 ** -20, offsets=od,
+                                                                  flags=fl, nflagged=nf), 1)[1])
+                    rows[-1]["monitor_us"] = round(tm * 1e6, 2)
+                    rows[-1]["monitor_flagged"] = int(nf.item())
+                plan.close()
+            del both, x, y
+            torch.cuda.empty_cache()
     print(json.dumps({"workload": "segmented twofold dot, 20,000 log-uniform segments in "
-                                  "[1, 2^20], seed 3", "peak_gb_s": HBM_PEAK_GBS, "rows": rows}),
-          flush=True)
+                                  "[1, 2^20] (and the 2^17-capped variant), seed 3",
+                      "peak_gb_s": HBM_PEAK_GBS, "device": device_info(torch, dev),
+                      "rows": rows}), flush=True)
 
 
 def calibrate_copy(torch, dev):
@@ -580,6 +594,7 @@ def main():
                                "HIP-graph replay)",
                    "n": N, "pairs": len(dev_in), "dots_per_step": ndots},
         "bitwise_repeatable": repeatable,
+        "device": device_info(torch, dev),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
