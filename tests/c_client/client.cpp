@@ -1,0 +1,120 @@
+// client.cpp: a native client of libtwofold.so through include/twofold.h
+// alone (no Python, no torch): device memory from hipMalloc, one stream,
+// the single-vector, segmented-plan and monitor entry points. Prints one
+// "name status value error" line per result, values as C99 hex floats, for
+// tests/test_gpu_c_client.py to check against exact rational sums.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include "twofold.h"
+
+#define HIP_OK(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      fprintf(stderr, "%s failed: %s\n", #call, hipGetErrorString(e_));          \
+      exit(2);                                                                    \
+    }                                                                             \
+  } while (0)
+
+static const int64_t kN = 1000003;
+
+int main(void) {
+  // x_i = 1 + (i mod 1000) * 2^-40 (rounds when summed), y_i = ((7 i) mod 201 - 100) / 32
+  double* hx = (double*)malloc(sizeof(double) * kN);
+  double* hy = (double*)malloc(sizeof(double) * kN);
+  float* hf = (float*)malloc(sizeof(float) * kN);
+  for (int64_t i = 0; i < kN; i++) {
+    hx[i] = 1.0 + (double)(i % 1000) * 0x1p-40;
+    hy[i] = (double)((7 * i) % 201 - 100) / 32.0;
+    hf[i] = (float)(1.0 + (double)(i % 1000) * 0x1p-20);
+  }
+  hipStream_t st;
+  HIP_OK(hipStreamCreate(&st));
+  double *x, *y;
+  float* xf;
+  twofold_f64_t* out64;
+  twofold_f32_t* out32;
+  HIP_OK(hipMalloc((void**)&x, sizeof(double) * kN));
+  HIP_OK(hipMalloc((void**)&y, sizeof(double) * kN));
+  HIP_OK(hipMalloc((void**)&xf, sizeof(float) * kN));
+  HIP_OK(hipMalloc((void**)&out64, sizeof(twofold_f64_t) * 8));
+  HIP_OK(hipMalloc((void**)&out32, sizeof(twofold_f32_t) * 2));
+  HIP_OK(hipMemcpy(x, hx, sizeof(double) * kN, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(y, hy, sizeof(double) * kN, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(xf, hf, sizeof(float) * kN, hipMemcpyHostToDevice));
+
+  size_t wsb = twofold_workspace_bytes_single(8, 1, TWOFOLD_RIGOROUS, kN, NULL);
+  size_t w2 = twofold_workspace_bytes_single(8, 0, TWOFOLD_RIGOROUS, kN, NULL);
+  size_t w3 = twofold_workspace_bytes_single(4, 0, TWOFOLD_RIGOROUS, kN, NULL);
+  if (w2 > wsb) wsb = w2;
+  if (w3 > wsb) wsb = w3;
+  void* ws;
+  HIP_OK(hipMalloc(&ws, wsb));
+
+  int rc[6];
+  rc[0] = twofold_sum_f64(x, kN, TWOFOLD_RIGOROUS, NULL, &out64[0], ws, wsb, st);
+  rc[1] = twofold_sum_f64(x, kN, TWOFOLD_PLAIN, NULL, &out64[1], ws, wsb, st);
+  rc[2] = twofold_dot_f64(x, y, kN, TWOFOLD_RIGOROUS, NULL, &out64[2], ws, wsb, st);
+  rc[3] = twofold_sum_f32(xf, kN, TWOFOLD_FAST, NULL, &out32[0], ws, wsb, st);
+
+  // a segmented plan over four segments (one empty), dots
+  const int64_t off_h[5] = {0, 10, 10, 1000, kN};
+  twofold_seg_plan_t* plan = NULL;
+  rc[4] = twofold_seg_plan_create(off_h, 4, 8, 1, TWOFOLD_RIGOROUS, NULL, &plan);
+  void* pws = NULL;
+  size_t pwsb = 0;
+  if (rc[4] == TWOFOLD_OK) {
+    pwsb = twofold_seg_plan_workspace_bytes(plan);
+    HIP_OK(hipMalloc(&pws, pwsb));
+    rc[4] = twofold_seg_plan_execute(plan, x, y, &out64[3], pws, pwsb, st);
+  }
+  // the precision monitor over the four segment results
+  int64_t* doff;
+  uint32_t* flags;
+  int64_t* nflag;
+  HIP_OK(hipMalloc((void**)&doff, sizeof(off_h)));
+  HIP_OK(hipMalloc((void**)&flags, 4 * sizeof(uint32_t)));
+  HIP_OK(hipMalloc((void**)&nflag, sizeof(int64_t)));
+  HIP_OK(hipMemcpy(doff, off_h, sizeof(off_h), hipMemcpyHostToDevice));
+  rc[5] = twofold_monitor(8, &out64[3], 4, doff, 0, 0.0, flags, nflag, st);
+  HIP_OK(hipStreamSynchronize(st));
+
+  twofold_f64_t r64[8];
+  twofold_f32_t r32[2];
+  uint32_t hflags[4];
+  int64_t hn;
+  HIP_OK(hipMemcpy(r64, out64, sizeof(r64), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(r32, out32, sizeof(r32), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(&hn, nflag, sizeof(hn), hipMemcpyDeviceToHost));
+
+  printf("sum_f64_rigorous %d %a %a\n", rc[0], r64[0].value, r64[0].error);
+  printf("sum_f64_plain %d %a %a\n", rc[1], r64[1].value, r64[1].error);
+  printf("dot_f64_rigorous %d %a %a\n", rc[2], r64[2].value, r64[2].error);
+  printf("sum_f32_fast %d %a %a\n", rc[3], (double)r32[0].value, (double)r32[0].error);
+  for (int s = 0; s < 4; s++)
+    printf("segdot_f64_rigorous_%d %d %a %a\n", s, rc[4], r64[3 + s].value, r64[3 + s].error);
+  printf("monitor %d %u %u %u %u %lld\n", rc[5], hflags[0], hflags[1], hflags[2], hflags[3],
+         (long long)hn);
+
+  HIP_OK(hipFree(x));
+  HIP_OK(hipFree(y));
+  HIP_OK(hipFree(xf));
+  HIP_OK(hipFree(out64));
+  HIP_OK(hipFree(out32));
+  HIP_OK(hipFree(ws));
+  if (pws) HIP_OK(hipFree(pws));
+  HIP_OK(hipFree(doff));
+  HIP_OK(hipFree(flags));
+  HIP_OK(hipFree(nflag));
+  if (plan) twofold_seg_plan_destroy(plan);
+  HIP_OK(hipStreamDestroy(st));
+  free(hx);
+  free(hy);
+  free(hf);
+  return 0;
+}
