@@ -259,6 +259,24 @@ single_kernel(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
   }
 }
 
+// Lane l of a combine over `stride` lanes: pairs l, l + stride, ... of
+// p[0 .. count), combined into (qs, qe) in that order (from +0). The loads run
+// up to eight pairs ahead of the combines, which stay in order.
+template <int M>
+__device__ __forceinline__ void combine_strided(const double2* __restrict__ p, int64_t count,
+                                                int64_t l, int64_t stride, double& qs, double& qe) {
+  constexpr int kAhead = 8;
+  for (int64_t i0 = l; i0 < count; i0 += kAhead * stride) {
+    double2 v[kAhead];
+#pragma unroll
+    for (int k = 0; k < kAhead; k++)
+      if (i0 + k * stride < count) v[k] = p[i0 + k * stride];
+#pragma unroll
+    for (int k = 0; k < kAhead; k++)
+      if (i0 + k * stride < count) combine<M>(qs, qe, v[k].x, v[k].y);
+  }
+}
+
 // Pass 2 (step 7): one block of kPass2Lanes threads combines the nparts
 // block pairs in binary64, lane l taking pairs l, l + 256, ... in order.
 template <typename T, int M>
@@ -266,10 +284,8 @@ __global__ void __launch_bounds__(kPass2Lanes)
 single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restrict__ out) {
   __shared__ double sh_s[kPass2Lanes / 64], sh_e[kPass2Lanes / 64];
   double qs = 0.0, qe = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kPass2Lanes) {
-    const double2 p = reinterpret_cast<const double2*>(part)[i];
-    combine<M>(qs, qe, p.x, p.y);
-  }
+  combine_strided<M>(reinterpret_cast<const double2*>(part), nparts, threadIdx.x, kPass2Lanes, qs,
+                     qe);
   wave_combine<M>(qs, qe);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) {
@@ -311,7 +327,10 @@ seg_kernel(const T* __restrict__ x, const T* __restrict__ y, const int64_t* __re
   if (status && *status != 0) return;  // invalid offsets: pass 2 reports NaN
   const int lane = threadIdx.x & 63;
   const int64_t wpb = blockDim.x >> 6;
-  const int64_t w = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6);
+  // the wave's index, made visibly uniform so its tile walk and the
+  // segment bounds below use scalar registers and scalar loads
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * wpb +
+                    __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   int64_t t0, t1, sg;
   if (wtab) {
     t0 = wtab[2 * w];
@@ -342,12 +361,36 @@ seg_kernel(const T* __restrict__ x, const T* __restrict__ y, const int64_t* __re
     t1 = (i1 < tbase[a1 + 1] - tbase[a1]) ? tbase[a1] + i1 : tbase[a1 + 1];
     sg = a0;
   }
+  if (t0 >= t1) return;
+  // Segment sg covers tiles [tb, tend) and elements [oa, ob). These stay in
+  // registers while the wave walks the segment's tiles; the next segment's
+  // bounds are requested at the start of every tile, so moving on to it
+  // does not wait for memory.
+  while (tbase[sg + 1] <= t0) sg++;
+  int64_t tb = tbase[sg], tend = tbase[sg + 1], oa = off[sg], ob = off[sg + 1];
+  int64_t nx_tend = tend, nx_ob = ob;
   for (int64_t t = t0; t < t1; t++) {
-    while (tbase[sg + 1] <= t) sg++;
-    const int64_t tb = tbase[sg];
-    const int64_t ntl = tbase[sg + 1] - tb;
-    const int64_t a = off[sg] + (t - tb) * TS;
-    const int64_t b = (off[sg + 1] < a + TS) ? off[sg + 1] : a + TS;
+    if (t >= tend) {
+      sg++;
+      tb = tend;
+      oa = ob;
+      tend = nx_tend;
+      ob = nx_ob;
+      while (tend <= t) {  // empty segments in between
+        sg++;
+        tb = tend;
+        oa = ob;
+        tend = tbase[sg + 1];
+        ob = off[sg + 1];
+      }
+    }
+    if (sg + 1 < nseg) {
+      nx_tend = tbase[sg + 2];
+      nx_ob = off[sg + 2];
+    }
+    const int64_t ntl = tend - tb;
+    const int64_t a = oa + (t - tb) * TS;
+    const int64_t b = (ob < a + TS) ? ob : a + TS;
     const T* xa = x + a;
     const T* ya = DOT ? y + a : nullptr;
     A s, e;
@@ -387,10 +430,7 @@ seg_pass2_kernel(const int64_t* __restrict__ tbase, int64_t nseg,
     return;
   }
   double qs = 0.0, qe = 0.0;
-  for (int64_t i = lane; i < ntl; i += 64) {
-    const double2 p = reinterpret_cast<const double2*>(slots)[tb + i];
-    combine<M>(qs, qe, p.x, p.y);
-  }
+  combine_strided<M>(reinterpret_cast<const double2*>(slots) + tb, ntl, lane, 64, qs, qe);
   wave_combine<M>(qs, qe);
   if (lane == 0) finalize_store<T, M>(out, sg, qs, qe);
 }
