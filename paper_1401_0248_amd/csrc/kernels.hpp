@@ -301,6 +301,205 @@ single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restric
 }
 
 // ---- segmented ---------------------------------------------------------------
+// Whether a lane keeps two rounds in registers (loads one round ahead).
+template <typename T, bool DOT, int U>
+constexpr bool rounds_ahead() {
+  return U * (DOT ? 2 : 1) <= 4;
+}
+
+// One wave's walk over its tiles. Segment sg covers tiles [tb, tend) and
+// elements [oa, ob); these stay in (scalar) registers while the wave walks
+// the segment's tiles, and the next segment's bounds are requested as soon
+// as a segment is entered, so moving on to it does not wait for memory.
+struct SegWalk {
+  const int64_t* __restrict__ off;
+  const int64_t* __restrict__ tbase;
+  int64_t nseg, TS, sg;
+  int64_t tb = 0, tend = 0, oa = 0, ob = 0, nx_tend = 0, nx_ob = 0;
+
+  __device__ __forceinline__ void prefetch() {
+    if (sg + 1 < nseg) {
+      nx_tend = tbase[sg + 2];
+      nx_ob = off[sg + 2];
+    }
+  }
+  // Enter the segment of tile t (sg at or before it).
+  __device__ __forceinline__ void start(int64_t t) {
+    while (tbase[sg + 1] <= t) sg++;
+    tb = tbase[sg];
+    tend = tbase[sg + 1];
+    oa = off[sg];
+    ob = off[sg + 1];
+    prefetch();
+  }
+  // Move on to tile t, at or after the current one.
+  __device__ __forceinline__ void to(int64_t t) {
+    if (t < tend) return;
+    sg++;
+    tb = tend;
+    oa = ob;
+    tend = nx_tend;
+    ob = nx_ob;
+    while (tend <= t) {  // empty segments in between
+      sg++;
+      tb = tend;
+      oa = ob;
+      tend = tbase[sg + 1];
+      ob = off[sg + 1];
+    }
+    prefetch();
+  }
+  __device__ __forceinline__ int64_t begin(int64_t t) const { return oa + (t - tb) * TS; }
+  __device__ __forceinline__ int64_t end(int64_t t) const {
+    const int64_t a = begin(t);
+    return ob < a + TS ? ob : a + TS;
+  }
+};
+
+// Steps 5 and the store of one tile's pair: a one-tile segment's pair is
+// finalized (step 8), a longer segment's goes to its tile slot.
+template <typename T, typename A, int M>
+__device__ __forceinline__ void tile_store(A s, A e, int lane, int64_t t, int64_t sg, int64_t ntl,
+                                           double* __restrict__ slots, void* __restrict__ out) {
+  wave_combine<M>(s, e);
+  if (lane == 0) {
+    if (ntl == 1)
+      finalize_store<T, M>(out, sg, static_cast<double>(s), static_cast<double>(e));
+    else
+      reinterpret_cast<double2*>(slots)[t] =
+          make_double2(static_cast<double>(s), static_cast<double>(e));
+  }
+}
+
+// The tiles [t0, t1) of one wave with loads one round ahead of the steps,
+// across tile boundaries too: while a tile's last (partial) round, tail and
+// combine run, the next tile's head, tail and first round are in flight.
+// Per tile, the steps are those of lane_reduce with L = 64, in the same
+// order, so every pair is the same.
+template <typename T, typename A, int M, bool DOT, bool YV, int U>
+__device__ __forceinline__ void seg_tiles_ahead(const T* __restrict__ x, const T* __restrict__ y,
+                                                SegWalk& wk, int64_t t0, int64_t t1, int lane,
+                                                double* __restrict__ slots, void* __restrict__ out) {
+  constexpr int W = 16 / static_cast<int>(sizeof(T));
+  constexpr int64_t PR = static_cast<int64_t>(U) * 64;  // vectors per round
+  using V = typename vec16<T>::type;
+  // The geometry of a tile [a, a + len): head elements, body vectors, full
+  // rounds (uniform across the wave).
+  struct Geo {
+    int64_t a, len, head, nv, full;
+  };
+  auto geo = [&](int64_t t) {
+    Geo g;
+    g.a = wk.begin(t);
+    g.len = wk.end(t) - g.a;
+    g.head = head_count(x + g.a, g.len);
+    g.nv = (g.len - g.head) / W;
+    g.full = g.nv / PR;
+    return g;
+  };
+  // A tile's first loads: head and tail elements, then round 0 (or, with no
+  // full round, the vectors of the partial round).
+  auto first_loads = [&](const Geo& g, V (&va)[U], V (&vb)[U], T& hx, T& hy, T& tx, T& ty) {
+    const T* xa = x + g.a;
+    const T* ya = DOT ? y + g.a : nullptr;
+    const T* xb = xa + g.head;
+    const T* yb = DOT ? ya + g.head : nullptr;
+    const int64_t tail0 = g.nv * W;
+    hx = hy = tx = ty = T(0);
+    if (lane < g.head) {
+      hx = load_nt(xa + lane);
+      if constexpr (DOT) hy = load_nt(ya + lane);
+    }
+    if (lane < (g.len - g.head) - tail0) {
+      tx = load_nt(xb + tail0 + lane);
+      if constexpr (DOT) ty = load_nt(yb + tail0 + lane);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t k = lane + u * 64;
+      if (g.full > 0 || k < g.nv) {
+        va[u] = load_vec<T, true>(xb, k);
+        if constexpr (DOT) vb[u] = load_vec<T, YV>(yb, k);
+      }
+    }
+  };
+  Geo g = geo(t0);
+  V va[U], vb[U];
+  T hx, hy, tx, ty;
+  first_loads(g, va, vb, hx, hy, tx, ty);
+  for (int64_t t = t0; t < t1; t++) {
+    const int64_t sg = wk.sg, ntl = wk.tend - wk.tb;
+    const T* xb = x + g.a + g.head;
+    const T* yb = DOT ? y + g.a + g.head : nullptr;
+    A cs[W], ce[W];
+#pragma unroll
+    for (int j = 0; j < W; j++) {
+      cs[j] = A(0);
+      ce[j] = A(0);
+    }
+    if (lane < g.head) step<M, DOT>(cs[0], ce[0], hx, hy);
+    int64_t k0 = lane;
+    for (int64_t q = 0; q < g.full; q++) {
+      const int64_t kn = k0 + PR;
+      V na[U], nb[U];
+      const bool whole = q + 1 < g.full;
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        if (whole || kn + u * 64 < g.nv) {
+          na[u] = load_vec<T, true>(xb, kn + u * 64);
+          if constexpr (DOT) nb[u] = load_vec<T, YV>(yb, kn + u * 64);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+#pragma unroll
+        for (int j = 0; j < W; j++)
+          step<M, DOT>(cs[j], ce[j], vget<T>(va[u], j), DOT ? vget<T>(vb[u], j) : T(0));
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        va[u] = na[u];
+        if constexpr (DOT) vb[u] = nb[u];
+      }
+      k0 = kn;
+    }
+    // The next tile's first loads go out before this tile's last round.
+    Geo gn = g;
+    V wa[U], wb[U];
+    T nhx = T(0), nhy = T(0), ntx = T(0), nty = T(0);
+    if (t + 1 < t1) {
+      wk.to(t + 1);
+      gn = geo(t + 1);
+      first_loads(gn, wa, wb, nhx, nhy, ntx, nty);
+    }
+    // last, partial round, then the tail
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (k0 + u * 64 < g.nv) {
+#pragma unroll
+        for (int j = 0; j < W; j++)
+          step<M, DOT>(cs[j], ce[j], vget<T>(va[u], j), DOT ? vget<T>(vb[u], j) : T(0));
+      }
+    }
+    if (lane < (g.len - g.head) - g.nv * W) step<M, DOT>(cs[0], ce[0], tx, ty);
+    A s = cs[0], e = ce[0];
+#pragma unroll
+    for (int j = 1; j < W; j++) combine<M>(s, e, cs[j], ce[j]);
+    tile_store<T, A, M>(s, e, lane, t, sg, ntl, slots, out);
+    g = gn;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      va[u] = wa[u];
+      if constexpr (DOT) vb[u] = wb[u];
+    }
+    hx = nhx;
+    hy = nhy;
+    tx = ntx;
+    ty = nty;
+  }
+}
+
+
 // Which wave takes which tile does not change any result; the assignment
 // balances bytes. A tile costs its length plus c0 = 64*W*U elements (one
 // round of its wave, standing for the tile's start-up), so the tiles before
@@ -362,46 +561,19 @@ seg_kernel(const T* __restrict__ x, const T* __restrict__ y, const int64_t* __re
     sg = a0;
   }
   if (t0 >= t1) return;
-  // Segment sg covers tiles [tb, tend) and elements [oa, ob). These stay in
-  // registers while the wave walks the segment's tiles; the next segment's
-  // bounds are requested at the start of every tile, so moving on to it
-  // does not wait for memory.
-  while (tbase[sg + 1] <= t0) sg++;
-  int64_t tb = tbase[sg], tend = tbase[sg + 1], oa = off[sg], ob = off[sg + 1];
-  int64_t nx_tend = tend, nx_ob = ob;
-  for (int64_t t = t0; t < t1; t++) {
-    if (t >= tend) {
-      sg++;
-      tb = tend;
-      oa = ob;
-      tend = nx_tend;
-      ob = nx_ob;
-      while (tend <= t) {  // empty segments in between
-        sg++;
-        tb = tend;
-        oa = ob;
-        tend = tbase[sg + 1];
-        ob = off[sg + 1];
-      }
-    }
-    if (sg + 1 < nseg) {
-      nx_tend = tbase[sg + 2];
-      nx_ob = off[sg + 2];
-    }
-    const int64_t ntl = tend - tb;
-    const int64_t a = oa + (t - tb) * TS;
-    const int64_t b = (ob < a + TS) ? ob : a + TS;
-    const T* xa = x + a;
-    const T* ya = DOT ? y + a : nullptr;
-    A s, e;
-    lane_reduce<T, A, M, DOT, YV, U>(xa, ya, b - a, head_count(xa, b - a), 64, lane, s, e);
-    wave_combine<M>(s, e);
-    if (lane == 0) {
-      if (ntl == 1)
-        finalize_store<T, M>(out, sg, static_cast<double>(s), static_cast<double>(e));
-      else
-        reinterpret_cast<double2*>(slots)[t] =
-            make_double2(static_cast<double>(s), static_cast<double>(e));
+  SegWalk wk{off, tbase, nseg, TS, sg};
+  wk.start(t0);
+  if constexpr (rounds_ahead<T, DOT, U>()) {
+    seg_tiles_ahead<T, A, M, DOT, YV, U>(x, y, wk, t0, t1, lane, slots, out);
+  } else {
+    for (int64_t t = t0; t < t1; t++) {
+      wk.to(t);
+      const int64_t a = wk.begin(t), b = wk.end(t);
+      const T* xa = x + a;
+      const T* ya = DOT ? y + a : nullptr;
+      A s, e;
+      lane_reduce<T, A, M, DOT, YV, U>(xa, ya, b - a, head_count(xa, b - a), 64, lane, s, e);
+      tile_store<T, A, M>(s, e, lane, t, wk.sg, wk.tend - wk.tb, slots, out);
     }
   }
 }

@@ -34,8 +34,8 @@ N_ILL = 1 << 24
 BENCH_TABLE = {(8, 1, "rigorous"): (256, 4, 256), (8, 1, "fast"): (256, 4, 256),
                (4, 1, "rigorous"): (256, 2, 512), (4, 1, "fast"): (256, 4, 256)}
 # segmented dots above 2^29 elements: (block_threads, unroll, grid, tile)
-SEG_TABLE = {(4, "rigorous"): (256, 8, 512, 65536), (4, "fast"): (256, 8, 512, 65536),
-             (8, "rigorous"): (256, 4, 256, 16384), (8, "fast"): (256, 8, 256, 32768)}
+SEG_TABLE = {(4, "rigorous"): (256, 4, 256, 65536), (4, "fast"): (256, 4, 256, 32768),
+             (8, "rigorous"): (256, 4, 256, 16384), (8, "fast"): (256, 4, 256, 16384)}
 
 
 def _u(dtype):
