@@ -128,6 +128,9 @@ def oracle_leg(host, gpu, launches, perm_host=None, perm_gpu=None):
                                          ex.A)
                 rows.setdefault("%s_rigorous_over_tree_bound" % key, []).append(
                     abs(ex.diff(p[0], p[1])) / tb)
+                u = bounds.unit_roundoff(dt)
+                rows.setdefault("%s_rigorous_over_4Nu2_bound" % key, []).append(
+                    abs(ex.diff(p[0], p[1])) / (4 * x.size * u * u * ex.A))
             if mode != "plain":
                 dv = ex.diff(p[0])  # v - S, rounded once
                 rows.setdefault("%s_%s_value" % (key, mode), []).append(abs(dv) / ex.A)
@@ -152,12 +155,13 @@ def oracle_leg(host, gpu, launches, perm_host=None, perm_gpu=None):
             pr["f32data_f64plain" if dt == np.float32 else "f64_double_word"] = float(
                 "%.3g" % (abs(ex.diff(p[0], p[1])) / ex.A))
     acc = {"measure": "median over conditions of |v + e - S| / sum|x y| (*_value: |v - S| / "
-                      "sum|x y|; *_q: e / (S - v); *_over_tree_bound: the largest |v + e - S| "
-                      "over the proven bound of the launch's reduction tree)"}
+                      "sum|x y|; *_q: e / (S - v); *_over_tree_bound and *_over_4Nu2_bound: the "
+                      "largest |v + e - S| over the proven bound of the launch's reduction "
+                      "tree, and over 4 N u^2 sum|x y|)"}
     for k, v in rows.items():
         if k.startswith("cond_"):
             acc[k] = ["%.3g" % c for c in v]
-        elif k.endswith("_over_tree_bound"):
+        elif k.endswith("_bound"):
             acc[k] = float("%.3g" % max(v))
         else:
             acc[k] = float("%.3g" % np.median(v))
