@@ -423,6 +423,54 @@ def segmented_batch(torch, tf, dev):
                       "rows": rows}), flush=True)
 
 
+def probes(torch, tf, dev):
+    """The instruments: the read probe (the paper's read1/read2) streams 1 GiB
+    (and a second 1 GiB) with the reductions' 16-byte non-temporal loads;
+    the compute probe (its p-functions) runs each form's step on
+    register-resident items, no memory traffic. Their ratio is each form's
+    arithmetic headroom over the HBM roofline. One JSON line."""
+    import numpy as np
+
+    rows = {"read": [], "compute": []}
+    nbytes = 1 << 30
+    x = torch.empty(nbytes // 4, dtype=torch.int32, device=dev).random_()
+    y = torch.empty(nbytes // 4, dtype=torch.int32, device=dev).random_()
+    for name, yy, tot in (("read1", None, nbytes), ("read2", y, 2 * nbytes)):
+        for bt, u, gb in ((256, 2, 512), (256, 4, 256), (256, 8, 256), (512, 2, 256),
+                          (512, 4, 256), (1024, 4, 256), (256, 4, 1024), (256, 8, 512)):
+            lc = tf.Launch(bt, u, gb, 0, 0)
+            sink = torch.empty(gb, dtype=torch.int64, device=dev)
+            t, tmin = graph_time(torch, lambda: (tf.probe_read(x, yy, lc, sink), 1)[1], reps=20)
+            rows["read"].append({"probe": name, "launch": [bt, u, gb], "us": round(t * 1e6, 2),
+                                 "gb_s": round(tot / t / 1e9, 1),
+                                 "hbm_frac": round(tot / t / 1e9 / HBM_PEAK_GBS, 4)})
+            log("  %s %s %.1f GB/s" % (name, (bt, u, gb), tot / t / 1e9))
+    del x, y
+    torch.cuda.empty_cache()
+    bt, gb, iters = 256, 2048, 2048
+    lc = tf.Launch(bt, 4, gb, 0, 0)
+    sink = torch.empty(2 * bt * gb, dtype=torch.float64, device=dev)
+    forms = ("plain", "fast", "rigorous", "kahan", "wide")
+    for dtype, tdt in ((np.float32, torch.float32), (np.float64, torch.float64)):
+        seed = (torch.rand(64, dtype=tdt, device=dev) - 0.5)
+        W = 16 // np.dtype(dtype).itemsize
+        items = bt * gb * iters * 4 * W
+        for op in ("sum", "dot"):
+            for form in forms + (("fast_rounded", "rigorous_rounded") if op == "dot" else ()):
+                t, _ = graph_time(torch, lambda: (tf.probe_compute(seed, op == "dot", form, iters,
+                                                                   lc, sink), 1)[1], reps=10)
+                gelem = items / t / 1e9
+                roof = HBM_PEAK_GBS / (np.dtype(dtype).itemsize * (2 if op == "dot" else 1))
+                rows["compute"].append({"dtype": np.dtype(dtype).name, "op": op, "form": form,
+                                        "gelem_s": round(gelem, 1),
+                                        "over_hbm_roofline": round(gelem / roof, 2)})
+                log("  compute %s %s %-16s %8.1f Gelem/s (%.1fx the HBM roofline)"
+                    % (np.dtype(dtype).name, op, form, gelem, gelem / roof))
+    print(json.dumps({"workload": "probes: read1/read2 over 1 GiB arrays, compute-only steps",
+                      "device": device_info(torch, dev), "peak_gb_s": HBM_PEAK_GBS,
+                      "rows": rows}), flush=True)
+
+
 def calibrate_copy(torch, dev):
     """A plain device copy of 256 MiB, five times: its FETCH_SIZE and
     WRITE_SIZE counters per dispatch calibrate the ones of the reductions."""
@@ -469,12 +517,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--workload", choices=("illcond", "sweep", "segmented", "precision"),
+    ap.add_argument("--workload", choices=("illcond", "sweep", "segmented", "precision", "probes"),
                     default="illcond",
                     help="illcond: the headline line (default); sweep: the roofline sweep of "
                          "every form at 4096, 2^20 and 1 GiB per vector; segmented: the "
                          "20,000-segment batch; precision: binary32 twofold against binary64 "
-                         "plain at N=2^26")
+                         "plain at N=2^26; probes: the read and compute instruments")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library's reduction runs on one device "
@@ -498,6 +546,9 @@ def main():
         return
     if args.workload == "precision":
         precision_study(torch, tf, dev, not args.no_cpu_baseline)
+        return
+    if args.workload == "probes":
+        probes(torch, tf, dev)
         return
     log("generating 12 ill-conditioned pairs, N=2^24")
     t0 = time.perf_counter()

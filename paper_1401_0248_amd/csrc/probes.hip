@@ -15,8 +15,16 @@ using namespace twofold;
 
 namespace {
 
-// Stream one or two arrays with 16-byte loads in the single-vector lane
-// order and fold every loaded bit into one word, so no load is dead code.
+// Stream one or two arrays with 16-byte non-temporal loads (the load the
+// reduction kernels use) in the single-vector lane order and fold every
+// loaded bit into one word, so no load is dead code.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 load_nt16(const uint4* p) {
+  const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 template <bool TWO, int U>
 __global__ void __launch_bounds__(1024)
 read_probe_kernel(const uint4* __restrict__ x, const uint4* __restrict__ y, int64_t nvec,
@@ -30,10 +38,10 @@ read_probe_kernel(const uint4* __restrict__ x, const uint4* __restrict__ y, int6
   for (int64_t q = 0; q < full; q++, k0 += per_round) {
     uint4 a[U], b[U];
 #pragma unroll
-    for (int u = 0; u < U; u++) a[u] = x[k0 + u * L];
+    for (int u = 0; u < U; u++) a[u] = load_nt16(x + k0 + u * L);
     if constexpr (TWO) {
 #pragma unroll
-      for (int u = 0; u < U; u++) b[u] = y[k0 + u * L];
+      for (int u = 0; u < U; u++) b[u] = load_nt16(y + k0 + u * L);
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -45,10 +53,10 @@ read_probe_kernel(const uint4* __restrict__ x, const uint4* __restrict__ y, int6
   for (int u = 0; u < U; u++) {
     const int64_t k = k0 + u * L;
     if (k < nvec) {
-      const uint4 a = x[k];
+      const uint4 a = load_nt16(x + k);
       acc |= a.x | a.y | a.z | a.w;
       if constexpr (TWO) {
-        const uint4 b = y[k];
+        const uint4 b = load_nt16(y + k);
         acc |= b.x | b.y | b.z | b.w;
       }
     }
@@ -67,7 +75,8 @@ read_probe_kernel(const uint4* __restrict__ x, const uint4* __restrict__ y, int6
 
 // The summation step of each mode applied to register-resident items: the
 // U*W items are loaded once; every iteration feeds all of them through the
-// lane's W chains again. The chains' results go to sink so nothing is dead.
+// lane's W chains again, the whole step included (a dot's product and
+// remainder too). The chains' results go to sink so nothing is dead.
 template <typename T, typename A, int M, bool DOT, int U>
 __global__ void __launch_bounds__(1024)
 compute_probe_kernel(const T* __restrict__ seed, int64_t iters, double* __restrict__ sink) {
@@ -88,6 +97,16 @@ compute_probe_kernel(const T* __restrict__ seed, int64_t iters, double* __restri
     ce[j] = A(0);
   }
   for (int64_t it = 0; it < iters; it++) {
+    // An empty register barrier: the compiler must assume the items changed,
+    // so the per-item work (products, FMA remainders) stays in the loop
+    // instead of being hoisted out of it. It emits no instruction.
+#pragma unroll
+    for (int u = 0; u < U; u++)
+#pragma unroll
+      for (int j = 0; j < W; j++) {
+        asm volatile("" : "+v"(xv[u][j]));
+        if constexpr (DOT) asm volatile("" : "+v"(yv[u][j]));
+      }
 #pragma unroll
     for (int u = 0; u < U; u++)
 #pragma unroll
