@@ -78,6 +78,8 @@
  *   lanes, lane l starting at (+0,+0) and combining tiles l, l+64, ... in
  *   tile order, then step 5, then step 8; an empty segment gives (+0,+0).
  *   Which wave handles which tile does not change the result.
+ * Multi-vector calls: vector v is reduced by steps 1-8 with the call's
+ * launch, exactly as a single-vector call with that launch reduces it.
  * Wide (sumd/dotd): binary32 data: as above with binary64 chains over
  * widened binary32 data and the plain combine; results are binary64 pairs
  * with error +0. binary64 data: as above with double-word chains: the step
@@ -103,11 +105,11 @@
  * preparation and holds nothing useful afterwards. Calls that may run at
  * the same time need separate workspaces. A single-vector call that runs
  * one block does not touch ws (it may then be NULL).
- * Kernels: a single-vector call is one kernel (one block) or two (blocks,
- * then the binary64 combine); a segmented call is the tiling kernel (device
- * offsets only), the tile kernel and the per-segment combine kernel. Later
- * kernels see earlier ones' results through the stream order alone: no
- * kernel waits on, or fences for, another block.
+ * Kernels: a single-vector or multi-vector call is one kernel (one block)
+ * or two (blocks, then the binary64 combine); a segmented call is the
+ * tiling kernel (device offsets only), the tile kernel and the per-segment
+ * combine kernel. Later kernels see earlier ones' results through the
+ * stream order alone: no kernel waits on, or fences for, another block.
  * Status: 0 on success, a negative TWOFOLD_E* code otherwise; arguments are
  * checked on the host before any HIP call, and nothing is launched on
  * error. Non-finite inputs give IEEE values and an unspecified error.
@@ -201,6 +203,34 @@ int twofold_sumd_f64(const double* x, int64_t n, const twofold_launch_t* launch,
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
 int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_launch_t* launch,
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- several vectors in one launch: count pairs into out[0..count) -------
+ * x[v], y[v] (device data pointers) and n[v] (lengths) are HOST arrays of
+ * count entries, 0 <= count <= 64; the vectors need not be contiguous, of
+ * equal length or equally aligned. out[v] is bitwise the pair the
+ * single-vector call (twofold_sum_* / twofold_dot_*) returns for vector v
+ * with the same launch; launch NULL takes the default launch of the longest
+ * vector. One set of grid_blocks blocks walks the vectors in order within
+ * one kernel, and one combine kernel finishes them all, so the per-call
+ * costs (kernel start and end, the combine kernel) are paid once per batch.
+ * Modes as the single-vector calls; TWOFOLD_WIDE is not accepted (one
+ * sumd/dotd call per vector). Workspace: twofold_workspace_bytes_multi
+ * (count times the single-vector workspace of the launch); count = 0 does
+ * nothing. */
+size_t twofold_workspace_bytes_multi(int dtype, int is_dot, int mode, const int64_t* n,
+                                     int64_t count, const twofold_launch_t* launch);
+int twofold_multisum_f32(const float* const* x, const int64_t* n, int64_t count, int mode,
+                         const twofold_launch_t* launch, twofold_f32_t* out, void* ws,
+                         size_t ws_bytes, void* stream);
+int twofold_multisum_f64(const double* const* x, const int64_t* n, int64_t count, int mode,
+                         const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                         size_t ws_bytes, void* stream);
+int twofold_multidot_f32(const float* const* x, const float* const* y, const int64_t* n,
+                         int64_t count, int mode, const twofold_launch_t* launch,
+                         twofold_f32_t* out, void* ws, size_t ws_bytes, void* stream);
+int twofold_multidot_f64(const double* const* x, const double* const* y, const int64_t* n,
+                         int64_t count, int mode, const twofold_launch_t* launch,
+                         twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- segmented (CSR) batches: nseg pairs into out[0..nseg) ---------------
  * offsets: device int64[nseg + 1], non-decreasing, offsets[0] >= 0 and

@@ -18,7 +18,8 @@ from ._lib import (FAST, FAST_ROUNDED, FLAG_ERROR, FLAG_LENGTH, FLAG_NONFINITE, 
                    RIGOROUS, RIGOROUS_ROUNDED, WIDE, Launch, TwofoldError, check)
 
 __all__ = [
-    "sum", "dot", "sumd", "dotd", "segsum", "segdot", "SegPlan", "Launch", "monitor",
+    "sum", "dot", "sumd", "dotd", "multisum", "multidot", "segsum", "segdot", "SegPlan",
+    "Launch", "monitor",
     "TwofoldError", "workspace", "default_launch", "probe_read", "probe_compute",
     "FLAG_ERROR", "FLAG_LENGTH", "FLAG_NONFINITE",
     "PLAIN", "FAST", "RIGOROUS", "WIDE", "KAHAN", "FAST_ROUNDED", "RIGOROUS_ROUNDED", "mode_id",
@@ -150,6 +151,61 @@ def dotd(x, y, launch=None, out=None, ws=None):
     float64 data with exact products in a double-word accumulator."""
     fn = "twofold_dotd_f32" if x.dtype == torch.float32 else "twofold_dotd_f64"
     return _single(fn, x, y, WIDE, launch, out, ws, torch.float64)
+
+
+MAX_MULTI = 64  # vectors per multi-vector call
+
+
+def _multi(fn, xs, ys, mode, launch, out, ws):
+    L = _lib.load()
+    xs = list(xs)
+    ys = None if ys is None else list(ys)
+    count = len(xs)
+    if not 1 <= count <= MAX_MULTI:
+        raise ValueError("twofold: a multi-vector call takes 1..%d vectors" % MAX_MULTI)
+    if ys is not None and len(ys) != count:
+        raise ValueError("twofold: xs and ys must have the same number of vectors")
+    for v in range(count):
+        _check_data(*([xs[v]] if ys is None else [xs[v], ys[v]]))
+        if xs[v].dtype != xs[0].dtype or xs[v].device != xs[0].device:
+            raise ValueError("twofold: all vectors must share dtype and device")
+    dev = xs[0].device
+    dt = xs[0].element_size()
+    m = mode_id(mode)
+    lp = _launch_ptr(launch)
+    ns = (ctypes.c_int64 * count)(*[x.numel() for x in xs])
+    xp = (ctypes.c_void_p * count)(*[x.data_ptr() for x in xs])
+    need = L.twofold_workspace_bytes_multi(dt, int(ys is not None), m, ctypes.cast(ns, ctypes.c_void_p),
+                                           count, lp)
+    if need == 0:
+        raise TwofoldError("twofold_workspace_bytes_multi", _lib.EINVAL)
+    if out is None:
+        out = torch.empty((count, 2), dtype=xs[0].dtype, device=dev)
+    if ws is None:
+        ws = workspace(need, dev)
+    args = [ctypes.cast(xp, ctypes.c_void_p)]
+    if ys is not None:
+        yp = (ctypes.c_void_p * count)(*[y.data_ptr() for y in ys])
+        args.append(ctypes.cast(yp, ctypes.c_void_p))
+    args += [ctypes.cast(ns, ctypes.c_void_p), count, m, lp, ctypes.c_void_p(out.data_ptr()),
+             ctypes.c_void_p(ws.ptr), ws.nbytes, _stream_ptr(dev)]
+    check(fn, getattr(L, fn)(*args))
+    return out
+
+
+def multisum(xs, mode="rigorous", launch=None, out=None, ws=None):
+    """Twofold sums of up to 64 vectors in one launch: a (count, 2) tensor,
+    row v bitwise the sum() of xs[v] with the same launch (default: the
+    launch of the longest vector)."""
+    fn = "twofold_multisum_f32" if xs[0].dtype == torch.float32 else "twofold_multisum_f64"
+    return _multi(fn, xs, None, mode, launch, out, ws)
+
+
+def multidot(xs, ys, mode="rigorous", launch=None, out=None, ws=None):
+    """Twofold dots of up to 64 vector pairs in one launch: a (count, 2)
+    tensor, row v bitwise the dot() of (xs[v], ys[v]) with the same launch."""
+    fn = "twofold_multidot_f32" if xs[0].dtype == torch.float32 else "twofold_multidot_f64"
+    return _multi(fn, xs, ys, mode, launch, out, ws)
 
 
 def _seg(x, y, offsets, mode, launch, out, ws):

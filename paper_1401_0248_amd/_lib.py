@@ -44,6 +44,11 @@ SIGNATURES = {
     "twofold_dotd_f32": (_int, [_vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
     "twofold_sumd_f64": (_int, [_vp, _i64, _LP, _vp, _vp, _sz, _vp]),
     "twofold_dotd_f64": (_int, [_vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_workspace_bytes_multi": (_sz, [_int, _int, _int, _vp, _i64, _LP]),
+    "twofold_multisum_f32": (_int, [_vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_multisum_f64": (_int, [_vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_multidot_f32": (_int, [_vp, _vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_multidot_f64": (_int, [_vp, _vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segsum_f32": (_int, [_vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segsum_f64": (_int, [_vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segdot_f32": (_int, [_vp, _vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),

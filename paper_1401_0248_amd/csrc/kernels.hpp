@@ -229,10 +229,13 @@ constexpr bool out_is_f64() {
 // otherwise it goes to part[] in binary64 and pass 2 combines the block
 // pairs in index order. The two passes are separate kernels: the kernel
 // boundary orders them, so no block ever waits on, or fences for, another.
+// Steps 1-6 for block `blk` of a grid of gridDim.x blocks over one vector;
+// the block pair goes to part[blk], or, with one block, finalized to
+// out[idx].
 template <typename T, typename A, int M, bool DOT, bool YV, int U>
-__global__ void __launch_bounds__(1024)
-single_kernel(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
-              double* __restrict__ part, void* __restrict__ out) {
+__device__ __forceinline__ void single_block(const T* __restrict__ x, const T* __restrict__ y,
+                                             int64_t n, double* __restrict__ part,
+                                             void* __restrict__ out, int64_t idx) {
   __shared__ A sh_s[16], sh_e[16];
   const int64_t L = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -251,11 +254,45 @@ single_kernel(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
     A bs = sh_s[0], be = sh_e[0];
     for (int w = 1; w < nw; w++) combine<M>(bs, be, sh_s[w], sh_e[w]);
     if (gridDim.x == 1) {
-      finalize_store<T, M>(out, 0, static_cast<double>(bs), static_cast<double>(be));
+      finalize_store<T, M>(out, idx, static_cast<double>(bs), static_cast<double>(be));
     } else {
       reinterpret_cast<double2*>(part)[blockIdx.x] =
           make_double2(static_cast<double>(bs), static_cast<double>(be));
     }
+  }
+}
+
+template <typename T, typename A, int M, bool DOT, bool YV, int U>
+__global__ void __launch_bounds__(1024)
+single_kernel(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
+              double* __restrict__ part, void* __restrict__ out) {
+  single_block<T, A, M, DOT, YV, U>(x, y, n, part, out, 0);
+}
+
+// ---- several vectors in one launch ------------------------------------------
+// Every block of a multi-vector call walks the vectors in order and reduces
+// its share of vector v exactly as a single-vector call with the same launch
+// does (steps 1-6; the block pairs of vector v at part[v * gridDim.x ...]).
+// So the launch streams all the vectors with one set of blocks, and its
+// start and end are paid once. The addresses and lengths travel in the
+// kernel arguments.
+constexpr int kMaxMulti = 64;
+
+template <typename T>
+struct MultiArgs {
+  const T* x[kMaxMulti];
+  const T* y[kMaxMulti];
+  int64_t n[kMaxMulti];
+};
+
+template <typename T, typename A, int M, bool DOT, bool YV, int U>
+__global__ void __launch_bounds__(1024)
+multi_kernel(const MultiArgs<T> args, int count, double* __restrict__ part,
+             void* __restrict__ out) {
+  for (int v = 0; v < count; v++) {
+    single_block<T, A, M, DOT, YV, U>(args.x[v], args.y[v], args.n[v],
+                                      part + 2 * static_cast<int64_t>(v) * gridDim.x, out, v);
+    __syncthreads();  // the block combine's LDS is reused for the next vector
   }
 }
 
@@ -277,15 +314,16 @@ __device__ __forceinline__ void combine_strided(const double2* __restrict__ p, i
   }
 }
 
-// Pass 2 (step 7): one block of kPass2Lanes threads combines the nparts
-// block pairs in binary64, lane l taking pairs l, l + 256, ... in order.
+// Pass 2 (step 7): block b of kPass2Lanes threads combines the nparts block
+// pairs of vector b (part[b * nparts ...]; one block for a single-vector
+// call) in binary64, lane l taking pairs l, l + 256, ... in order.
 template <typename T, int M>
 __global__ void __launch_bounds__(kPass2Lanes)
 single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restrict__ out) {
   __shared__ double sh_s[kPass2Lanes / 64], sh_e[kPass2Lanes / 64];
   double qs = 0.0, qe = 0.0;
-  combine_strided<M>(reinterpret_cast<const double2*>(part), nparts, threadIdx.x, kPass2Lanes, qs,
-                     qe);
+  combine_strided<M>(reinterpret_cast<const double2*>(part) + static_cast<int64_t>(blockIdx.x) * nparts,
+                     nparts, threadIdx.x, kPass2Lanes, qs, qe);
   wave_combine<M>(qs, qe);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) {
@@ -296,7 +334,7 @@ single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restric
   if (threadIdx.x == 0) {
     double V = sh_s[0], E = sh_e[0];
     for (int w = 1; w < kPass2Lanes / 64; w++) combine<M>(V, E, sh_s[w], sh_e[w]);
-    finalize_store<T, M>(out, 0, V, E);
+    finalize_store<T, M>(out, blockIdx.x, V, E);
   }
 }
 

@@ -86,6 +86,99 @@ int single_entry(const T* x, const T* y, int64_t n, int mode, const twofold_laun
                                 static_cast<hipStream_t>(stream));
 }
 
+// ---- several vectors in one launch ------------------------------------------
+template <typename T, typename A, int M, bool DOT, bool YV>
+int launch_multi_u(const MultiArgs<T>& a, int64_t count, const twofold_launch_t& lc,
+                   double* part, void* out, hipStream_t st) {
+  const dim3 grid(lc.grid_blocks), block(lc.block_threads);
+  const int c = int(count);
+  switch (lc.unroll) {
+    case 1: multi_kernel<T, A, M, DOT, YV, 1><<<grid, block, 0, st>>>(a, c, part, out); break;
+    case 2: multi_kernel<T, A, M, DOT, YV, 2><<<grid, block, 0, st>>>(a, c, part, out); break;
+    case 4: multi_kernel<T, A, M, DOT, YV, 4><<<grid, block, 0, st>>>(a, c, part, out); break;
+    default: multi_kernel<T, A, M, DOT, YV, 8><<<grid, block, 0, st>>>(a, c, part, out); break;
+  }
+  if (launch_status()) return TWOFOLD_EHIP;
+  if (lc.grid_blocks > 1) {
+    single_pass2_kernel<T, M><<<dim3(unsigned(count)), dim3(kPass2Lanes), 0, st>>>(
+        part, lc.grid_blocks, out);
+    return launch_status();
+  }
+  return TWOFOLD_OK;
+}
+
+template <typename T, typename A, int M, bool DOT>
+int launch_multi(const MultiArgs<T>& a, int64_t count, bool yv, const twofold_launch_t& lc,
+                 double* part, void* out, hipStream_t st) {
+  if constexpr (DOT) {
+    if (!yv) return launch_multi_u<T, A, M, DOT, false>(a, count, lc, part, out, st);
+  }
+  return launch_multi_u<T, A, M, DOT, true>(a, count, lc, part, out, st);
+}
+
+template <typename T, bool DOT>
+int multi_by_mode(int mode, const MultiArgs<T>& a, int64_t count, bool yv,
+                  const twofold_launch_t& lc, double* part, void* out, hipStream_t st) {
+  switch (mode) {
+    case kPlain: return launch_multi<T, T, kPlain, DOT>(a, count, yv, lc, part, out, st);
+    case kFast: return launch_multi<T, T, kFast, DOT>(a, count, yv, lc, part, out, st);
+    case kRigorous: return launch_multi<T, T, kRigorous, DOT>(a, count, yv, lc, part, out, st);
+    case kKahan: return launch_multi<T, T, kKahan, DOT>(a, count, yv, lc, part, out, st);
+    case kFastRounded:
+      if constexpr (DOT) return launch_multi<T, T, kFastRounded, DOT>(a, count, yv, lc, part, out, st);
+      return TWOFOLD_EINVAL;
+    case kRigorousRounded:
+      if constexpr (DOT)
+        return launch_multi<T, T, kRigorousRounded, DOT>(a, count, yv, lc, part, out, st);
+      return TWOFOLD_EINVAL;
+    default: return TWOFOLD_EINVAL;  // the wider accumulator: one sumd/dotd call per vector
+  }
+}
+
+// The launch of a multi-vector call: the single-vector one for the longest
+// vector (or the given one).
+int resolve_multi(int dtype, bool is_dot, int mode, const int64_t* n, int64_t count,
+                  const twofold_launch_t* launch, twofold_launch_t* lc) {
+  int64_t nmax = 0;
+  for (int64_t v = 0; v < count; v++) nmax = n[v] > nmax ? n[v] : nmax;
+  return resolve_single(dtype, is_dot, mode, nmax, launch, lc);
+}
+
+template <typename T, bool DOT>
+int multi_entry(const T* const* x, const T* const* y, const int64_t* n, int64_t count, int mode,
+                const twofold_launch_t* launch, void* out, void* ws, size_t ws_bytes,
+                void* stream) {
+  const int dtype = int(sizeof(T));
+  if (count < 0 || count > kMaxMulti || !out) return TWOFOLD_EINVAL;
+  if (count > 0 && (!x || !n || (DOT && !y))) return TWOFOLD_EINVAL;
+  if (!mode_ok(dtype, DOT, mode) || mode == kWide) return TWOFOLD_EINVAL;
+  if (!elem_aligned(out, dtype)) return TWOFOLD_EALIGN;
+  MultiArgs<T> a;
+  bool yv = true;
+  for (int64_t v = 0; v < count; v++) {
+    if (!valid_count(n[v]) || (!x[v] && n[v] > 0) || (DOT && !y[v] && n[v] > 0))
+      return TWOFOLD_EINVAL;
+    if (!elem_aligned(x[v], dtype) || (DOT && !elem_aligned(y[v], dtype))) return TWOFOLD_EALIGN;
+    a.x[v] = x[v];
+    a.y[v] = DOT ? y[v] : nullptr;
+    a.n[v] = n[v];
+    if (DOT && !y_vector_ok(x[v], y[v])) yv = false;
+  }
+  for (int64_t v = count; v < kMaxMulti; v++) {
+    a.x[v] = nullptr;
+    a.y[v] = nullptr;
+    a.n[v] = 0;
+  }
+  if (count == 0) return TWOFOLD_OK;
+  twofold_launch_t lc;
+  const int rc = resolve_multi(dtype, DOT, mode, n, count, launch, &lc);
+  if (rc) return rc;
+  if (lc.grid_blocks > 1 && !ws_ok(ws, ws_bytes, multi_ws_bytes(lc, count)))
+    return TWOFOLD_EWORKSPACE;
+  return multi_by_mode<T, DOT>(mode, a, count, yv, lc, static_cast<double*>(ws), out,
+                               static_cast<hipStream_t>(stream));
+}
+
 }  // namespace
 
 extern "C" {
@@ -145,6 +238,39 @@ int twofold_sumd_f64(const double* x, int64_t n, const twofold_launch_t* launch,
 int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_launch_t* launch,
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
   return single_entry<double, true>(x, y, n, kWide, launch, out, ws, ws_bytes, stream);
+}
+
+size_t twofold_workspace_bytes_multi(int dtype, int is_dot, int mode, const int64_t* n,
+                                     int64_t count, const twofold_launch_t* launch) {
+  if (!valid_dtype(dtype) || count < 0 || count > kMaxMulti || (count > 0 && !n) ||
+      !mode_ok(dtype, is_dot != 0, mode) || mode == kWide)
+    return 0;
+  for (int64_t v = 0; v < count; v++)
+    if (!valid_count(n[v])) return 0;
+  twofold_launch_t lc;
+  if (resolve_multi(dtype, is_dot != 0, mode, n, count, launch, &lc)) return 0;
+  return multi_ws_bytes(lc, count);
+}
+
+int twofold_multisum_f32(const float* const* x, const int64_t* n, int64_t count, int mode,
+                         const twofold_launch_t* launch, twofold_f32_t* out, void* ws,
+                         size_t ws_bytes, void* stream) {
+  return multi_entry<float, false>(x, nullptr, n, count, mode, launch, out, ws, ws_bytes, stream);
+}
+int twofold_multisum_f64(const double* const* x, const int64_t* n, int64_t count, int mode,
+                         const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                         size_t ws_bytes, void* stream) {
+  return multi_entry<double, false>(x, nullptr, n, count, mode, launch, out, ws, ws_bytes, stream);
+}
+int twofold_multidot_f32(const float* const* x, const float* const* y, const int64_t* n,
+                         int64_t count, int mode, const twofold_launch_t* launch,
+                         twofold_f32_t* out, void* ws, size_t ws_bytes, void* stream) {
+  return multi_entry<float, true>(x, y, n, count, mode, launch, out, ws, ws_bytes, stream);
+}
+int twofold_multidot_f64(const double* const* x, const double* const* y, const int64_t* n,
+                         int64_t count, int mode, const twofold_launch_t* launch,
+                         twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
+  return multi_entry<double, true>(x, y, n, count, mode, launch, out, ws, ws_bytes, stream);
 }
 
 const char* twofold_strerror(int status) {

@@ -178,3 +178,42 @@ def test_probe_argument_checks():
     assert L.twofold_probe_compute(8, 1, 7, fake, 10, ctypes.byref(lc), fake, None) == EINVAL
 
 
+
+
+def test_multi_argument_checks():
+    L = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    ws = ctypes.c_void_p(0x100000)
+    P = ctypes.c_void_p * 3
+    N = ctypes.c_int64 * 3
+    xs, ys, ns = P(0x10000, 0x20000, 0x30000), P(0x40000, 0x50000, 0x60000), N(10, 0, 7)
+    big = 1 << 20
+    assert L.twofold_multidot_f64(xs, ys, ns, 65, 2, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_multidot_f64(xs, ys, ns, -1, 2, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_multidot_f64(None, ys, ns, 3, 2, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_multidot_f64(xs, None, ns, 3, 2, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_multidot_f64(xs, ys, None, 3, 2, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_multidot_f64(xs, ys, ns, 3, 3, None, fake, ws, big, None) == EINVAL  # wide
+    assert L.twofold_multisum_f32(xs, ns, 3, 5, None, fake, ws, big, None) == EINVAL  # rounded
+    assert L.twofold_multisum_f32(xs, ns, 3, 2, None, None, ws, big, None) == EINVAL
+    # count 0: nothing to do, nothing launched
+    assert L.twofold_multisum_f32(None, None, 0, 2, None, fake, ws, big, None) == 0
+    # a null data pointer only for an empty vector
+    assert L.twofold_multisum_f64(P(0, 0x20000, 0x30000), ns, 3, 2, None, fake, ws, big,
+                                  None) == EINVAL
+    # misaligned data, too many elements
+    assert L.twofold_multisum_f64(P(0x10000, 0x20000, 0x30004), ns, 3, 2, None, fake, ws, big,
+                                  None) == EALIGN
+    assert L.twofold_multidot_f32(xs, P(0x40000, 0x50002, 0x60000), ns, 3, 2, None, fake, ws,
+                                  big, None) == EALIGN
+    assert L.twofold_multisum_f32(xs, N(10, (1 << 56) + 1, 7), 3, 2, None, fake, ws, big,
+                                  None) == EINVAL
+    # workspace: count times the single-vector one of the longest vector's launch
+    long_ns = N(1 << 24, 5, 1 << 20)
+    one = L.twofold_workspace_bytes_single(8, 1, 2, 1 << 24, None)
+    three = L.twofold_workspace_bytes_multi(8, 1, 2, long_ns, 3, None)
+    assert one > 256 and three >= 3 * (one - 255)
+    assert L.twofold_multidot_f64(xs, ys, long_ns, 3, 2, None, fake, ws, three - 256, None) == \
+        EWORKSPACE
+    assert L.twofold_workspace_bytes_multi(8, 1, 3, long_ns, 3, None) == 0  # wide
+    assert L.twofold_workspace_bytes_multi(8, 1, 2, long_ns, 65, None) == 0
