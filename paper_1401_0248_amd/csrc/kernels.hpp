@@ -163,22 +163,42 @@ __device__ __forceinline__ void lane_reduce(const T* __restrict__ x, const T* __
   };
   int64_t k0 = g;
   if constexpr (kAhead) {
-    V a[U], b[U];  // the round whose steps run next
-    load_round(a, b, k0, full > 0);
-    if (has_head) step<M, DOT>(cs[0], ce[0], hx, hy);
-    for (int64_t q = 0; q < full; q++) {
-      const int64_t kn = k0 + per_round;
-      V na[U], nb[U];
-      load_round(na, nb, kn, q + 1 < full);
-      step_round(a, b, k0, true);
-#pragma unroll
-      for (int u = 0; u < U; u++) {
-        a[u] = na[u];
-        if constexpr (DOT) b[u] = nb[u];
+    // Two round buffers used in turn (a0/b0, a1/b1), so that no register
+    // is copied while its load may still be in flight: the loads of round
+    // q + 1 stay outstanding while the steps of round q run.
+    V a0[U], b0[U], a1[U], b1[U];
+    if (full == 0) {
+      load_round(a0, b0, k0, false);
+      if (has_head) step<M, DOT>(cs[0], ce[0], hx, hy);
+      step_round(a0, b0, k0, false);  // the partial round alone
+    } else {
+      load_round(a0, b0, k0, true);
+      if (has_head) step<M, DOT>(cs[0], ce[0], hx, hy);
+      // a0/b0 holds full round q on entry; rounds q + 1 and q + 2 are full
+      int64_t q = 0;
+      for (; q + 2 < full; q += 2) {
+        load_round(a1, b1, k0 + per_round, true);
+        step_round(a0, b0, k0, true);
+        k0 += per_round;
+        load_round(a0, b0, k0 + per_round, true);
+        step_round(a1, b1, k0, true);
+        k0 += per_round;
       }
-      k0 = kn;
+      if (q + 1 < full) {  // two full rounds left, then the partial one
+        load_round(a1, b1, k0 + per_round, true);
+        step_round(a0, b0, k0, true);
+        k0 += per_round;
+        load_round(a0, b0, k0 + per_round, false);
+        step_round(a1, b1, k0, true);
+        k0 += per_round;
+        step_round(a0, b0, k0, false);
+      } else {  // one full round left, then the partial one
+        load_round(a1, b1, k0 + per_round, false);
+        step_round(a0, b0, k0, true);
+        k0 += per_round;
+        step_round(a1, b1, k0, false);
+      }
     }
-    step_round(a, b, k0, false);  // last, partial round
   } else {
     if (has_head) step<M, DOT>(cs[0], ce[0], hx, hy);
     for (int64_t q = 0; q < full; q++, k0 += per_round) {
@@ -476,30 +496,47 @@ __device__ __forceinline__ void seg_tiles_ahead(const T* __restrict__ x, const T
       ce[j] = A(0);
     }
     if (lane < g.head) step<M, DOT>(cs[0], ce[0], hx, hy);
+    // Rounds in turn through va/vb and na/nb: the loads of the next round
+    // are issued before the steps of the current one and no round is copied
+    // while in flight. A tile with an odd number of full rounds ends with
+    // its partial round in na/nb, which is then moved to va/vb once.
     int64_t k0 = lane;
-    for (int64_t q = 0; q < g.full; q++) {
-      const int64_t kn = k0 + PR;
-      V na[U], nb[U];
-      const bool whole = q + 1 < g.full;
+    V na[U], nb[U];
+    auto load_into = [&](V (&a)[U], V (&b)[U], int64_t k, bool whole) {
 #pragma unroll
       for (int u = 0; u < U; u++) {
-        if (whole || kn + u * 64 < g.nv) {
-          na[u] = load_vec<T, true>(xb, kn + u * 64);
-          if constexpr (DOT) nb[u] = load_vec<T, YV>(yb, kn + u * 64);
+        if (whole || k + u * 64 < g.nv) {
+          a[u] = load_vec<T, true>(xb, k + u * 64);
+          if constexpr (DOT) b[u] = load_vec<T, YV>(yb, k + u * 64);
         }
       }
+    };
+    auto step_full = [&](const V (&a)[U], const V (&b)[U]) {
 #pragma unroll
       for (int u = 0; u < U; u++) {
 #pragma unroll
         for (int j = 0; j < W; j++)
-          step<M, DOT>(cs[j], ce[j], vget<T>(va[u], j), DOT ? vget<T>(vb[u], j) : T(0));
+          step<M, DOT>(cs[j], ce[j], vget<T>(a[u], j), DOT ? vget<T>(b[u], j) : T(0));
       }
+    };
+    int64_t q = 0;
+    for (; q + 2 <= g.full; q += 2) {  // va holds full round q; round q + 1 is full
+      load_into(na, nb, k0 + PR, true);
+      step_full(va, vb);
+      k0 += PR;
+      load_into(va, vb, k0 + PR, q + 2 < g.full);
+      step_full(na, nb);
+      k0 += PR;
+    }
+    if (q < g.full) {  // one full round left
+      load_into(na, nb, k0 + PR, false);
+      step_full(va, vb);
+      k0 += PR;
 #pragma unroll
       for (int u = 0; u < U; u++) {
         va[u] = na[u];
         if constexpr (DOT) vb[u] = nb[u];
       }
-      k0 = kn;
     }
     // The next tile's first loads go out before this tile's last round.
     Geo gn = g;
