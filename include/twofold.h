@@ -210,9 +210,11 @@ int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_
  * equal length or equally aligned. out[v] is bitwise the pair the
  * single-vector call (twofold_sum_* / twofold_dot_*) returns for vector v
  * with the same launch; launch NULL takes the default launch of the longest
- * vector. One set of grid_blocks blocks walks the vectors in order within
- * one kernel, and one combine kernel finishes them all, so the per-call
- * costs (kernel start and end, the combine kernel) are paid once per batch.
+ * vector. All vectors go through one kernel: short ones (at most 64 MiB
+ * read each) side by side with a set of grid_blocks blocks each, longer
+ * ones in turn through one set. One combine kernel finishes them all, so
+ * the per-call costs (kernel start and end, the combine kernel) are paid
+ * once per batch.
  * Modes as the single-vector calls; TWOFOLD_WIDE is not accepted (one
  * sumd/dotd call per vector). Workspace: twofold_workspace_bytes_multi
  * (count times the single-vector workspace of the launch); count = 0 does

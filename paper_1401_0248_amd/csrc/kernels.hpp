@@ -249,19 +249,12 @@ constexpr bool out_is_f64() {
 // otherwise it goes to part[] in binary64 and pass 2 combines the block
 // pairs in index order. The two passes are separate kernels: the kernel
 // boundary orders them, so no block ever waits on, or fences for, another.
-// Steps 1-6 for block `blk` of a grid of gridDim.x blocks over one vector;
-// the block pair goes to part[blk], or, with one block, finalized to
-// out[idx].
-template <typename T, typename A, int M, bool DOT, bool YV, int U>
-__device__ __forceinline__ void single_block(const T* __restrict__ x, const T* __restrict__ y,
-                                             int64_t n, double* __restrict__ part,
-                                             void* __restrict__ out, int64_t idx) {
+// Steps 5-6 for the lane pairs (s, e) of one vector: the block pair goes to
+// part[blockIdx.x], or, with one block, finalized to out[idx].
+template <typename T, typename A, int M>
+__device__ __forceinline__ void block_store(A s, A e, double* __restrict__ part,
+                                            void* __restrict__ out, int64_t idx) {
   __shared__ A sh_s[16], sh_e[16];
-  const int64_t L = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t head = head_count(x, n);
-  A s, e;
-  lane_reduce<T, A, M, DOT, YV, U>(x, y, n, head, L, g, s, e);
   wave_combine<M>(s, e);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nw = blockDim.x >> 6;
@@ -282,6 +275,20 @@ __device__ __forceinline__ void single_block(const T* __restrict__ x, const T* _
   }
 }
 
+// Steps 1-6 for block blockIdx.x of a grid of gridDim.x blocks over one
+// vector.
+template <typename T, typename A, int M, bool DOT, bool YV, int U>
+__device__ __forceinline__ void single_block(const T* __restrict__ x, const T* __restrict__ y,
+                                             int64_t n, double* __restrict__ part,
+                                             void* __restrict__ out, int64_t idx) {
+  const int64_t L = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t head = head_count(x, n);
+  A s, e;
+  lane_reduce<T, A, M, DOT, YV, U>(x, y, n, head, L, g, s, e);
+  block_store<T, A, M>(s, e, part, out, idx);
+}
+
 template <typename T, typename A, int M, bool DOT, bool YV, int U>
 __global__ void __launch_bounds__(1024)
 single_kernel(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
@@ -289,13 +296,21 @@ single_kernel(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
   single_block<T, A, M, DOT, YV, U>(x, y, n, part, out, 0);
 }
 
+// Whether a lane keeps two rounds in registers (loads one round ahead).
+template <typename T, bool DOT, int U>
+constexpr bool rounds_ahead() {
+  return U * (DOT ? 2 : 1) <= 4;
+}
+
 // ---- several vectors in one launch ------------------------------------------
-// Every block of a multi-vector call walks the vectors in order and reduces
-// its share of vector v exactly as a single-vector call with the same launch
-// does (steps 1-6; the block pairs of vector v at part[v * gridDim.x ...]).
-// So the launch streams all the vectors with one set of blocks, and its
-// start and end are paid once. The addresses and lengths travel in the
-// kernel arguments.
+// A multi-vector launch has gridDim.y sets of gridDim.x blocks. Set r takes
+// vectors r, r + gridDim.y, ... in turn, and its block b reduces its share
+// of vector v exactly as block b of a single-vector call with the same
+// launch does (steps 1-6; the block pairs of vector v at
+// part[v * gridDim.x ...]). One set walking all the vectors streams them
+// like one long vector; one set per vector runs short vectors side by side.
+// Either way every pair is the same. The addresses and lengths travel in
+// the kernel arguments.
 constexpr int kMaxMulti = 64;
 
 template <typename T>
@@ -309,7 +324,7 @@ template <typename T, typename A, int M, bool DOT, bool YV, int U>
 __global__ void __launch_bounds__(1024)
 multi_kernel(const MultiArgs<T> args, int count, double* __restrict__ part,
              void* __restrict__ out) {
-  for (int v = 0; v < count; v++) {
+  for (int v = blockIdx.y; v < count; v += gridDim.y) {
     single_block<T, A, M, DOT, YV, U>(args.x[v], args.y[v], args.n[v],
                                       part + 2 * static_cast<int64_t>(v) * gridDim.x, out, v);
     __syncthreads();  // the block combine's LDS is reused for the next vector
@@ -359,11 +374,6 @@ single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restric
 }
 
 // ---- segmented ---------------------------------------------------------------
-// Whether a lane keeps two rounds in registers (loads one round ahead).
-template <typename T, bool DOT, int U>
-constexpr bool rounds_ahead() {
-  return U * (DOT ? 2 : 1) <= 4;
-}
 
 // One wave's walk over its tiles. Segment sg covers tiles [tb, tend) and
 // elements [oa, ob); these stay in (scalar) registers while the wave walks
@@ -519,16 +529,25 @@ __device__ __forceinline__ void seg_tiles_ahead(const T* __restrict__ x, const T
           step<M, DOT>(cs[j], ce[j], vget<T>(a[u], j), DOT ? vget<T>(b[u], j) : T(0));
       }
     };
+    // (only whole rounds inside the loop, so its loads carry no condition
+    // and the waits count exactly)
     int64_t q = 0;
-    for (; q + 2 <= g.full; q += 2) {  // va holds full round q; round q + 1 is full
+    for (; q + 2 < g.full; q += 2) {  // va holds full round q; rounds q + 1, q + 2 are full
       load_into(na, nb, k0 + PR, true);
       step_full(va, vb);
       k0 += PR;
-      load_into(va, vb, k0 + PR, q + 2 < g.full);
+      load_into(va, vb, k0 + PR, true);
       step_full(na, nb);
       k0 += PR;
     }
-    if (q < g.full) {  // one full round left
+    if (q + 1 < g.full) {  // two full rounds left
+      load_into(na, nb, k0 + PR, true);
+      step_full(va, vb);
+      k0 += PR;
+      load_into(va, vb, k0 + PR, false);
+      step_full(na, nb);
+      k0 += PR;
+    } else if (q < g.full) {  // one full round left
       load_into(na, nb, k0 + PR, false);
       step_full(va, vb);
       k0 += PR;

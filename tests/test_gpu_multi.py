@@ -2,7 +2,8 @@
 twofold_multidot_*): every row is bitwise the order model's single-vector
 result for that vector under the call's launch, and bitwise the
 single-vector call with the same launch, whatever the other vectors' lengths
-and alignments."""
+and alignments, and whether the vectors run side by side (short ones) or
+one after another (long ones)."""
 import numpy as np
 import pytest
 import torch
@@ -73,10 +74,13 @@ def test_multi_rounded_dots_vs_model(dtype, mode):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("is_dot", [False, True])
-def test_multi_equals_single_calls_default_launch(dtype, is_dot):
+@pytest.mark.parametrize("longest", [(1 << 22) + 5, (1 << 24) + 9])
+def test_multi_equals_single_calls_default_launch(dtype, is_dot, longest):
     # several ill-sized long vectors: the default launch is the longest one's,
-    # and every row equals the single call made with that launch
-    lengths = [(1 << 22) + 5, (1 << 21) + 3, 0, 12345, 1 << 22]
+    # and every row equals the single call made with that launch. Vectors
+    # that read up to 64 MiB run side by side, longer ones one after another
+    # (2^24 + 9 elements take the second way for every type and operation)
+    lengths = [longest, (1 << 21) + 3, 0, 12345, 1 << 22]
     _, _, dx, dy, _ = _vectors(dtype, is_dot, lengths, 300)
     for mode in ("fast", "rigorous"):
         out = _call(dx, dy, mode)
