@@ -1,6 +1,7 @@
 // client.cpp: a native client of libtwofold.so through include/twofold.h
 // alone (no Python, no torch): device memory from hipMalloc, one stream,
-// the single-vector, segmented-plan and monitor entry points. Prints one
+// the single-vector, multi-vector, segmented-plan and monitor entry points.
+// Prints one
 // "name status value error" line per result, values as C99 hex floats, for
 // tests/test_gpu_c_client.py to check against exact rational sums.
 #include <hip/hip_runtime.h>
@@ -81,6 +82,19 @@ int main(void) {
   HIP_OK(hipMalloc((void**)&nflag, sizeof(int64_t)));
   HIP_OK(hipMemcpy(doff, off_h, sizeof(off_h), hipMemcpyHostToDevice));
   rc[5] = twofold_monitor(8, &out64[3], 4, doff, 0, 0.0, flags, nflag, st);
+
+  // three dots in one multi-vector call: the whole pair, the pair from
+  // element 1 on (both 8 bytes past a 16-byte line) and its first 1000
+  // elements
+  const double* mx[3] = {x, x + 1, x};
+  const double* my[3] = {y, y + 1, y};
+  const int64_t mn[3] = {kN, kN - 1, 1000};
+  size_t mwsb = twofold_workspace_bytes_multi(8, 1, TWOFOLD_RIGOROUS, mn, 3, NULL);
+  void* mws;
+  twofold_f64_t* outm;
+  HIP_OK(hipMalloc(&mws, mwsb));
+  HIP_OK(hipMalloc((void**)&outm, sizeof(twofold_f64_t) * 3));
+  const int rcm = twofold_multidot_f64(mx, my, mn, 3, TWOFOLD_RIGOROUS, NULL, outm, mws, mwsb, st);
   HIP_OK(hipStreamSynchronize(st));
 
   twofold_f64_t r64[8];
@@ -100,6 +114,10 @@ int main(void) {
     printf("segdot_f64_rigorous_%d %d %a %a\n", s, rc[4], r64[3 + s].value, r64[3 + s].error);
   printf("monitor %d %u %u %u %u %lld\n", rc[5], hflags[0], hflags[1], hflags[2], hflags[3],
          (long long)hn);
+  twofold_f64_t rm[3];
+  HIP_OK(hipMemcpy(rm, outm, sizeof(rm), hipMemcpyDeviceToHost));
+  for (int v = 0; v < 3; v++)
+    printf("multidot_f64_rigorous_%d %d %a %a\n", v, rcm, rm[v].value, rm[v].error);
 
   HIP_OK(hipFree(x));
   HIP_OK(hipFree(y));
@@ -111,6 +129,8 @@ int main(void) {
   HIP_OK(hipFree(doff));
   HIP_OK(hipFree(flags));
   HIP_OK(hipFree(nflag));
+  HIP_OK(hipFree(mws));
+  HIP_OK(hipFree(outm));
   if (plan) twofold_seg_plan_destroy(plan);
   HIP_OK(hipStreamDestroy(st));
   free(hx);

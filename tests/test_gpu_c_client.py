@@ -76,6 +76,13 @@ def test_native_client_matches_the_oracle():
     for s in range(4):
         assert _pair(rows["segdot_f64_rigorous_%d" % s]) == (seg[s][0], seg[s][1]), s
     assert tuple(seg[1]) == (0.0, 0.0)
+    # the multi-vector call: each row is the order model's single-vector
+    # result under the default launch of the longest vector
+    lc = _launch(0, 8, 1, 2, N)
+    for v, (a, n) in enumerate(((0, N), (1, N - 1), (0, 1000))):
+        want = oracle.model_single("rigorous", x[a:a + n], y[a:a + n], a % 2, lc.block_threads,
+                                   lc.unroll, lc.grid_blocks)
+        assert _pair(rows["multidot_f64_rigorous_%d" % v]) == (want[0], want[1]), v
     m = rows["monitor"]
     assert int(m[0]) == 0
     flags = monitor.flags(seg, np.diff(OFF), 0.0, np.float64)
