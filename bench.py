@@ -177,8 +177,9 @@ def oracle_leg(host, gpu, launches, perm_host=None, perm_gpu=None):
 def precision_study(torch, tf, dev, with_oracle):
     """The binary32 precision form: N = 2^26 binary32 pairs x = m 2^k, y
     likewise (m uniform(-1, 1), k uniform integer in [-20, 20], seed 2).
-    Times the binary32 plain, fast and rigorous twofold dots, the binary64
-    plain dot of the same binary32 data (dotd) and the binary64 plain and
+    Times the binary32 plain, fast and rigorous twofold dots, the mixed
+    form (binary32 rigorous value, binary64 error term), the binary64 plain
+    dot of the same binary32 data (dotd) and the binary64 plain and
     rigorous dots over a binary64 copy (twice the bytes), HIP-graph replay.
     Its CPU-baseline leg grades every result against the exact accumulator
     and times the oracle's sequential rigorous dot on the same data. One
@@ -193,11 +194,14 @@ def precision_study(torch, tf, dev, with_oracle):
     x64, y64 = xd.double(), yd.double()
     L = tf._lib.load()
     ws = tf.Workspace(max(L.twofold_workspace_bytes_single(sz, 1, m, n, None)
-                          for sz, m in ((4, 0), (4, 1), (4, 2), (4, 3), (8, 0), (8, 2), (8, 3))),
+                          for sz, m in ((4, 0), (4, 1), (4, 2), (4, 3), (4, 7), (8, 0), (8, 2),
+                                        (8, 3))),
                       dev)
     forms = [("f32 plain", lambda o: tf.dot(xd, yd, "plain", out=o, ws=ws), 4),
              ("f32 fast twofold", lambda o: tf.dot(xd, yd, "fast", out=o, ws=ws), 4),
              ("f32 rigorous twofold", lambda o: tf.dot(xd, yd, "rigorous", out=o, ws=ws), 4),
+             ("f32 rigorous twofold, f64 error term (mixed)",
+              lambda o: tf.dot_mixed(xd, yd, out=o, ws=ws), 8),
              ("f64 plain on f32 data (dotd)", lambda o: tf.dotd(xd, yd, out=o, ws=ws), 8),
              ("f64 plain on an f64 copy", lambda o: tf.dot(x64, y64, "plain", out=o, ws=ws), 8),
              ("f64 rigorous on an f64 copy", lambda o: tf.dot(x64, y64, "rigorous", out=o, ws=ws),
@@ -307,8 +311,9 @@ def to_device_chunks(torch, chunks, n, dtype, dev):
 
 def roofline_sweep(torch, tf, dev):
     """Every form of sum and dot (plain, fast, rigorous, Kahan, the wide
-    accumulator for binary32 data, and for dots the paper's rounded-product
-    fast and rigorous forms), binary32 and binary64, at N = 4096, 2^20 and
+    accumulator, for binary32 data the mixed form, and for dots the paper's
+    rounded-product fast and rigorous forms), binary32 and binary64, at
+    N = 4096, 2^20 and
     1 GiB per vector, uniform(-1, 1) data of seed 1, tuned default
     launches, HIP-graph replay: the method comparison of the paper's
     Table 1 on one MI355X. One JSON line."""
@@ -330,9 +335,11 @@ def roofline_sweep(torch, tf, dev):
                 forms = FORMS + ("kahan", "wide")
                 if op == "dot":
                     forms += ("fast_rounded", "rigorous_rounded")
+                if size == 4:
+                    forms += ("mixed",)
                 for form in forms:
                     out = torch.empty(2, dtype=torch.float64, device=dev)
-                    o = out if (size == 8 or form == "wide") else out.view(torch.float32)[:2]
+                    o = out if (size == 8 or form in ("wide", "mixed")) else out.view(torch.float32)[:2]
                     need = tf._lib.load().twofold_workspace_bytes_single(
                         size, op == "dot", tf.mode_id(form), n, None)
                     ws = tf.Workspace(need, dev)
@@ -341,6 +348,9 @@ def roofline_sweep(torch, tf, dev):
                         if form == "wide":
                             (tf.dotd(x, y, out=o, ws=ws) if op == "dot"
                              else tf.sumd(x, out=o, ws=ws))
+                        elif form == "mixed":
+                            (tf.dot_mixed(x, y, out=o, ws=ws) if op == "dot"
+                             else tf.sum_mixed(x, out=o, ws=ws))
                         elif op == "dot":
                             tf.dot(x, y, form, out=o, ws=ws)
                         else:

@@ -23,6 +23,15 @@
  *   TWOFOLD_FAST_ROUNDED, TWOFOLD_RIGOROUS_ROUNDED  dots only: the paper's
  *                     own dot rule, the rounded product as the item and its
  *                     rounding not tracked (same value as the FMA forms).
+ *   TWOFOLD_MIXED     binary32 data only: the rigorous form with its error
+ *                     term in binary64. The value is the binary32 rigorous
+ *                     value, bit for bit; each step's exact round-off (a
+ *                     binary32 number) is added to a binary64 error, so the
+ *                     error term no longer rounds at binary32 precision.
+ *                     Results are binary64 pairs (twofold_sum_mixed_f32,
+ *                     twofold_dot_mixed_f32, plans). This mode uses binary64
+ *                     arithmetic inside binary32 reductions, as the paper's
+ *                     sumd/dotd comparators do.
  * Dot products: the paper substitutes the rounded product a[i]*b[i] for the
  * data item (end of "Algorithms"). This library also captures the product's
  * rounding: p = fl(x*y), pi = fma(x, y, -p), x*y = p + pi exactly unless the
@@ -80,6 +89,14 @@
  *   Which wave handles which tile does not change the result.
  * Multi-vector calls: vector v is reduced by steps 1-8 with the call's
  * launch, exactly as a single-vector call with that launch reduces it.
+ * Mixed (binary32 data): chains and combines as the rigorous mode, with the
+ * value in binary32 and the error in binary64: the step is t = s + item,
+ * yt = t - s, dy = item - yt, ds = s - (t - yt) in binary32, then
+ * e = e + (double)(ds + dy), for dots e = e + ((double)(ds + dy) +
+ * (double)pi) with pi = fma(x, y, -p) in binary32; combine is the binary32
+ * two-sum of the values (x, y) and e = (e1 + e2) + (double)y. Step 7 uses
+ * the binary64 combine of the rigorous mode; step 8 gives value
+ * fl32(V) and error (V - value) + E, both binary64.
  * Wide (sumd/dotd): binary32 data: as above with binary64 chains over
  * widened binary32 data and the plain combine; results are binary64 pairs
  * with error +0. binary64 data: as above with double-word chains: the step
@@ -137,7 +154,8 @@ enum {
                        binary32 data, double-word for binary64 data */
   TWOFOLD_KAHAN = 4,
   TWOFOLD_FAST_ROUNDED = 5,
-  TWOFOLD_RIGOROUS_ROUNDED = 6
+  TWOFOLD_RIGOROUS_ROUNDED = 6,
+  TWOFOLD_MIXED = 7
 };
 
 enum {
@@ -199,6 +217,13 @@ int twofold_dotd_f32(const float* x, const float* y, int64_t n, const twofold_la
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
 /* The same for binary64 data, in double-word arithmetic (the paper's quad
  * accumulator, see above): out = (h, l), h + l the double-word sum. */
+/* Mode TWOFOLD_MIXED on binary32 data (see the modes above): out->value is
+ * the binary32 rigorous value, out->error the binary64 error term. */
+int twofold_sum_mixed_f32(const float* x, int64_t n, const twofold_launch_t* launch,
+                          twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
+int twofold_dot_mixed_f32(const float* x, const float* y, int64_t n,
+                          const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                          size_t ws_bytes, void* stream);
 int twofold_sumd_f64(const double* x, int64_t n, const twofold_launch_t* launch,
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
 int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_launch_t* launch,
@@ -215,8 +240,8 @@ int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_
  * ones in turn through one set. One combine kernel finishes them all, so
  * the per-call costs (kernel start and end, the combine kernel) are paid
  * once per batch.
- * Modes as the single-vector calls; TWOFOLD_WIDE is not accepted (one
- * sumd/dotd call per vector). Workspace: twofold_workspace_bytes_multi
+ * Modes as the single-vector calls; TWOFOLD_WIDE and TWOFOLD_MIXED are not
+ * accepted (one sumd/dotd or mixed call per vector). Workspace: twofold_workspace_bytes_multi
  * (count times the single-vector workspace of the launch); count = 0 does
  * nothing. */
 size_t twofold_workspace_bytes_multi(int dtype, int is_dot, int mode, const int64_t* n,
@@ -238,8 +263,8 @@ int twofold_multidot_f64(const double* const* x, const double* const* y, const i
  * offsets: device int64[nseg + 1], non-decreasing, offsets[0] >= 0 and
  * offsets[nseg] <= n_total (the length of x and y). Checked on the device:
  * on violation every out[s] is NaN.
- * mode TWOFOLD_WIDE is accepted here for binary64 data only (binary32
- * data: see the plan interface). */
+ * mode TWOFOLD_WIDE is accepted here for binary64 data only, and
+ * TWOFOLD_MIXED not at all (binary32 data: see the plan interface). */
 int twofold_segsum_f32(const float* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
                        int mode, const twofold_launch_t* launch, twofold_f32_t* out, void* ws,
                        size_t ws_bytes, void* stream);
@@ -261,8 +286,8 @@ int twofold_segdot_f64(const double* x, const double* y, int64_t n_total, const 
  * pairs of the tiles of multi-tile segments.
  * dtype 4 or 8; mode TWOFOLD_* (ROUNDED forms only for dots).
  * execute: the tile kernel (persistent waves) and the combine kernel on
- * stream, no host work in between; out is twofold_f32_t[nseg] for
- * dtype 4 modes PLAIN/FAST/RIGOROUS, twofold_f64_t[nseg] otherwise; y must
+ * stream, no host work in between; out is twofold_f64_t[nseg] for binary64
+ * data and for modes WIDE and MIXED, twofold_f32_t[nseg] otherwise; y must
  * be NULL for sums and given for dots (is_dot at creation). Capturable.
  * A plan must not execute on two streams at once. */
 typedef struct twofold_seg_plan twofold_seg_plan_t;

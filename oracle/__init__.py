@@ -26,9 +26,9 @@ import numpy as np
 
 from . import build as _build
 
-PLAIN, FAST, RIGOROUS, WIDE, KAHAN, FAST_ROUNDED, RIGOROUS_ROUNDED = 0, 1, 2, 3, 4, 5, 6
+PLAIN, FAST, RIGOROUS, WIDE, KAHAN, FAST_ROUNDED, RIGOROUS_ROUNDED, MIXED = 0, 1, 2, 3, 4, 5, 6, 7
 MODES = {"plain": PLAIN, "fast": FAST, "rigorous": RIGOROUS, "wide": WIDE, "kahan": KAHAN,
-         "fast_rounded": FAST_ROUNDED, "rigorous_rounded": RIGOROUS_ROUNDED}
+         "fast_rounded": FAST_ROUNDED, "rigorous_rounded": RIGOROUS_ROUNDED, "mixed": MIXED}
 
 _lib = None
 

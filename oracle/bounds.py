@@ -117,3 +117,23 @@ def dw_bound(Lc, D, A):
     if r >= 1:
         return math.inf
     return r * A / (1 - r)
+
+
+def mixed_bound(Lc, D, A):
+    """Bound on |v + e - S| for the mixed mode (binary32 data, binary32
+    value, binary64 error) over a tree of depths (Lc, D).
+
+    The value path is the binary32 rigorous one, so its exact terms add up
+    to at most T = u32 (Lc + D + 1) (1 + g32(Lc + D)) (1 + u32) A, as in
+    tree_bound. They are summed in binary64: a term meets at most
+    h = Lc + 2D + 3 binary64 roundings (one for the remainder plus the
+    product remainder, Lc chain additions, two per combine, one in the
+    finalize), so |V + E - S| <= g64(h) T. The finalize e = (V - v) + E
+    rounds once more: at most u64 (|V - v| + |E|) <= u64 (u32 grow A +
+    (1 + g64(h)) T)."""
+    u32 = unit_roundoff(np.float32)
+    u64 = unit_roundoff(np.float64)
+    grow = (1 + g(Lc + D, u32)) * (1 + u32)
+    T = u32 * (Lc + D + 1) * grow * A
+    h = Lc + 2 * D + 3
+    return g(h, u64) * T + u64 * (u32 * grow * A + (1 + g(h, u64)) * T)

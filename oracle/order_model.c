@@ -24,7 +24,12 @@
  *      error fl32((V - value) + E), both operations in binary64 (error +0
  *      for the plain and wide modes, whose pairs carry no error).
  * The wide mode on binary64 data keeps double-word chains and combines
- * them with AccurateDWPlusDW in every step above (dw.h).
+ * them with AccurateDWPlusDW in every step above (dw.h). The mixed mode
+ * (binary32 data) keeps binary64 chains whose value is always a binary32
+ * number: steps and combines before step 7 do the rigorous form's
+ * arithmetic on the value in binary32 and add its exact remainders to the
+ * binary64 error; step 7 is the binary64 combine; finalize gives value
+ * fl32(V) and error (V - value) + E in binary64.
  * Segmented, tiles of TS elements (TS a multiple of 64*W): segment s has
  * ceil(len_s/TS) tiles; each tile is reduced by one 64-lane wave with
  * steps 1-5 on the tile's range; a one-tile segment's pair is finalized
@@ -46,10 +51,12 @@
 #define MODE_KAHAN 4
 #define MODE_FAST_ROUNDED 5
 #define MODE_RIGOROUS_ROUNDED 6
+/* binary32 data only: the rigorous form with a binary64 error term */
+#define MODE_MIXED 7
 /* The wide mode on binary64 data: a double-word accumulator (dw.h). The
  * public mode number is MODE_WIDE for both data types; this one is the
  * model's own name for the binary64 case. */
-#define MODE_DW 7
+#define MODE_DW 8
 #define HAS_ERROR(m) ((m) != MODE_PLAIN && (m) != MODE_WIDE)
 
 static void combine64(int mode, double* s1, double* e1, double s2, double e2) {
@@ -112,6 +119,13 @@ static void finalize(int mode, int tsize, double V, double E, double* out2) {
     out2[1] = E;
     return;
   }
+  if (mode == MODE_MIXED) {
+    /* value fl32(V); the error stays binary64: (V - value) + E */
+    double v = (double)(float)V;
+    out2[0] = v;
+    out2[1] = (V - v) + E;
+    return;
+  }
   float v = (float)V;
   float e = 0.0f;
   if (HAS_ERROR(mode)) {
@@ -144,7 +158,7 @@ static void finalize(int mode, int tsize, double V, double E, double* out2) {
 #undef FMA_T
 #undef NAME
 
-/* binary32 data, binary64 accumulators (mode WIDE only). */
+/* binary32 data, binary64 accumulators (modes WIDE and MIXED). */
 #define T float
 #define A double
 #define FMA_T fmaf
@@ -157,7 +171,8 @@ static void finalize(int mode, int tsize, double V, double E, double* out2) {
 
 static int valid_common(int dtype, int mode, int is_dot, int U) {
   if (dtype != 4 && dtype != 8) return 0;
-  if (mode < MODE_PLAIN || mode > MODE_RIGOROUS_ROUNDED) return 0;
+  if (mode < MODE_PLAIN || mode > MODE_MIXED) return 0;
+  if (mode == MODE_MIXED && dtype != 4) return 0;
   if ((mode == MODE_FAST_ROUNDED || mode == MODE_RIGOROUS_ROUNDED) && !is_dot) return 0;
   if (U < 1 || U > 64) return 0;
   return 1;
@@ -175,7 +190,7 @@ int oracle_model_single(int dtype, int mode, const void* x, const void* y, int64
   if (dtype == 8)
     return m64_single(mode, is_dot, (const double*)x, (const double*)y, n, x_misalign,
                       block_threads, unroll, grid_blocks, out2, viol);
-  if (mode == MODE_WIDE)
+  if (mode == MODE_WIDE || mode == MODE_MIXED)
     return mw_single(mode, is_dot, (const float*)x, (const float*)y, n, x_misalign,
                      block_threads, unroll, grid_blocks, out2, viol);
   return m32_single(mode, is_dot, (const float*)x, (const float*)y, n, x_misalign,
@@ -196,7 +211,7 @@ int oracle_model_seg(int dtype, int mode, const void* x, const void* y,
   if (dtype == 8)
     return m64_seg(mode, is_dot, (const double*)x, (const double*)y, offsets, nseg, x_misalign,
                    unroll, tile_elems, out, viol);
-  if (mode == MODE_WIDE)
+  if (mode == MODE_WIDE || mode == MODE_MIXED)
     return mw_seg(mode, is_dot, (const float*)x, (const float*)y, offsets, nseg, x_misalign,
                   unroll, tile_elems, out, viol);
   return m32_seg(mode, is_dot, (const float*)x, (const float*)y, offsets, nseg, x_misalign,

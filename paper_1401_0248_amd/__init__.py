@@ -14,19 +14,21 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (FAST, FAST_ROUNDED, FLAG_ERROR, FLAG_LENGTH, FLAG_NONFINITE, KAHAN, PLAIN,
+from ._lib import (FAST, FAST_ROUNDED, FLAG_ERROR, FLAG_LENGTH, FLAG_NONFINITE, KAHAN, MIXED, PLAIN,
                    RIGOROUS, RIGOROUS_ROUNDED, WIDE, Launch, TwofoldError, check)
 
 __all__ = [
-    "sum", "dot", "sumd", "dotd", "multisum", "multidot", "segsum", "segdot", "SegPlan",
+    "sum", "dot", "sumd", "dotd", "sum_mixed", "dot_mixed", "multisum", "multidot", "segsum",
+    "segdot", "SegPlan",
     "Launch", "monitor",
     "TwofoldError", "workspace", "default_launch", "probe_read", "probe_compute",
     "FLAG_ERROR", "FLAG_LENGTH", "FLAG_NONFINITE",
-    "PLAIN", "FAST", "RIGOROUS", "WIDE", "KAHAN", "FAST_ROUNDED", "RIGOROUS_ROUNDED", "mode_id",
+    "PLAIN", "FAST", "RIGOROUS", "WIDE", "KAHAN", "FAST_ROUNDED", "RIGOROUS_ROUNDED", "MIXED",
+    "mode_id",
 ]
 
 _MODES = {"plain": PLAIN, "fast": FAST, "rigorous": RIGOROUS, "wide": WIDE, "kahan": KAHAN,
-          "fast_rounded": FAST_ROUNDED, "rigorous_rounded": RIGOROUS_ROUNDED}
+          "fast_rounded": FAST_ROUNDED, "rigorous_rounded": RIGOROUS_ROUNDED, "mixed": MIXED}
 
 
 def mode_id(mode):
@@ -117,7 +119,8 @@ def _single(fn, x, y, mode, launch, out, ws, out_dtype):
     if y is not None:
         args.append(ctypes.c_void_p(y.data_ptr()))
     args.append(n)
-    if not fn.startswith(("twofold_sumd_", "twofold_dotd_")):
+    if not fn.startswith(("twofold_sumd_", "twofold_dotd_", "twofold_sum_mixed_",
+                          "twofold_dot_mixed_")):
         args.append(m)
     args += [lp, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.ptr), ws.nbytes,
              _stream_ptr(dev)]
@@ -208,6 +211,21 @@ def multidot(xs, ys, mode="rigorous", launch=None, out=None, ws=None):
     return _multi(fn, xs, ys, mode, launch, out, ws)
 
 
+def sum_mixed(x, launch=None, out=None, ws=None):
+    """Rigorous twofold sum of float32 data with a float64 error term: a
+    float64 tensor([value, error]) whose value is sum(x, "rigorous")'s."""
+    if x.dtype != torch.float32:
+        raise TypeError("twofold: the mixed form takes float32 data")
+    return _single("twofold_sum_mixed_f32", x, None, MIXED, launch, out, ws, torch.float64)
+
+
+def dot_mixed(x, y, launch=None, out=None, ws=None):
+    """Rigorous twofold dot of float32 data with a float64 error term."""
+    if x.dtype != torch.float32:
+        raise TypeError("twofold: the mixed form takes float32 data")
+    return _single("twofold_dot_mixed_f32", x, y, MIXED, launch, out, ws, torch.float64)
+
+
 def _seg(x, y, offsets, mode, launch, out, ws):
     L = _lib.load()
     _check_data(*([x] if y is None else [x, y]))
@@ -276,7 +294,7 @@ class SegPlan:
 
     @property
     def out_dtype(self):
-        return torch.float64 if (self.dtype == 8 or self.mode == WIDE) else torch.float32
+        return torch.float64 if (self.dtype == 8 or self.mode in (WIDE, MIXED)) else torch.float32
 
     def execute(self, x, y=None, out=None, ws=None):
         _check_data(*([x] if y is None else [x, y]))

@@ -10,7 +10,7 @@ import os
 from . import build as _build
 
 OK, EINVAL, EWORKSPACE, EHIP, EALIGN, EOFFSETS = 0, -1, -2, -3, -4, -5
-PLAIN, FAST, RIGOROUS, WIDE, KAHAN, FAST_ROUNDED, RIGOROUS_ROUNDED = 0, 1, 2, 3, 4, 5, 6
+PLAIN, FAST, RIGOROUS, WIDE, KAHAN, FAST_ROUNDED, RIGOROUS_ROUNDED, MIXED = 0, 1, 2, 3, 4, 5, 6, 7
 FLAG_ERROR, FLAG_LENGTH, FLAG_NONFINITE = 1, 2, 4
 
 # Every symbol the public header declares, with (restype, argtypes).
@@ -44,6 +44,8 @@ SIGNATURES = {
     "twofold_dotd_f32": (_int, [_vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
     "twofold_sumd_f64": (_int, [_vp, _i64, _LP, _vp, _vp, _sz, _vp]),
     "twofold_dotd_f64": (_int, [_vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_sum_mixed_f32": (_int, [_vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_dot_mixed_f32": (_int, [_vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
     "twofold_workspace_bytes_multi": (_sz, [_int, _int, _int, _vp, _i64, _LP]),
     "twofold_multisum_f32": (_int, [_vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_multisum_f64": (_int, [_vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),

@@ -19,6 +19,11 @@ namespace twofold {
 // (kWide itself); for binary64 data, where the paper used quad precision,
 // a double-word (double-double) sum, kDoubleDouble (internal only: the
 // public mode is TWOFOLD_WIDE for both data types).
+// kMixed (binary32 data only): the rigorous form with its error term in
+// binary64. The value chain is the binary32 rigorous one; each step's exact
+// round-off (and a dot's product remainder), binary32 numbers, are added to
+// a binary64 error. Both parts live in binary64 registers, the value always
+// holding a binary32 number.
 enum Mode : int {
   kPlain = 0,
   kFast = 1,
@@ -27,11 +32,16 @@ enum Mode : int {
   kKahan = 4,
   kFastRounded = 5,
   kRigorousRounded = 6,
-  kDoubleDouble = 7
+  kMixed = 7,
+  kDoubleDouble = 8
 };
 
 // Modes whose pairs carry an error (all but plain and wide).
 constexpr bool has_error(int m) { return m != kPlain && m != kWide; }
+
+// The combine used once block pairs are binary64 (step 7): a mixed pair's
+// value is then a binary64 sum, combined like a rigorous pair.
+constexpr int pass2_mode(int m) { return m == kMixed ? kRigorous : m; }
 
 __device__ __forceinline__ float fma_rn(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_rn(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -91,6 +101,23 @@ __device__ __forceinline__ void step(A& s, A& e, T xv, T yv) {
     } else {
       dw_add_fp(s, e, xv);
     }
+  } else if constexpr (M == kMixed) {
+    // Example 3 in binary32 on the value; its exact round-off ds + dy and
+    // the product remainder join the binary64 error
+    static_assert(sizeof(T) == 4 && sizeof(A) == 8, "mixed: binary32 data, binary64 registers");
+    const float sf = static_cast<float>(s);  // exact: s holds a binary32 number
+    const float p = DOT ? xv * yv : xv;
+    const float t = sf + p;
+    const float yt = t - sf;
+    const float dy = p - yt;
+    const float ds = sf - (t - yt);
+    if constexpr (DOT) {
+      const float pi = fma_rn(xv, yv, -p);
+      e = e + (static_cast<double>(ds + dy) + static_cast<double>(pi));
+    } else {
+      e = e + static_cast<double>(ds + dy);
+    }
+    s = static_cast<double>(t);
   } else if constexpr (M == kPlain) {
     T item = DOT ? xv * yv : xv;
     s = s + item;
@@ -145,6 +172,18 @@ __device__ __forceinline__ void combine(A& s1, A& e1, A s2, A e2) {
     e1 = A(0);
   } else if constexpr (M == kDoubleDouble) {
     dw_add_dw(s1, e1, s2, e2);  // double-word pairs add as double-word numbers
+  } else if constexpr (M == kMixed) {
+    // two-sum of the binary32 values in binary32, remainder into the
+    // binary64 error
+    const float a = static_cast<float>(s1), b = static_cast<float>(s2);
+    const float x = a + b;
+    const float bp = x - a;
+    const float ap = x - bp;
+    const float bh = b - bp;
+    const float ah = a - ap;
+    const float y = ah + bh;
+    e1 = (e1 + e2) + static_cast<double>(y);
+    s1 = static_cast<double>(x);
   } else {
     A x = s1 + s2;
     A bp = x - s1;

@@ -224,6 +224,10 @@ __device__ __forceinline__ void finalize_store(void* __restrict__ out, int64_t i
                                                double E) {
   if constexpr (sizeof(T) == 8 || M == kWide) {
     reinterpret_cast<double2*>(out)[idx] = make_double2(V, E);
+  } else if constexpr (M == kMixed) {
+    // value fl32(V), error (V - value) + E in binary64 (V - value is exact)
+    const double v = static_cast<double>(static_cast<float>(V));
+    reinterpret_cast<double2*>(out)[idx] = make_double2(v, (V - v) + E);
   } else {
     const float v = static_cast<float>(V);
     float e = 0.0f;
@@ -241,7 +245,7 @@ __device__ __forceinline__ void store_nan_pair(void* out, int64_t idx, bool f64_
 
 template <typename T, int M>
 constexpr bool out_is_f64() {
-  return sizeof(T) == 8 || M == kWide;
+  return sizeof(T) == 8 || M == kWide || M == kMixed;
 }
 
 // ---- single vector ----------------------------------------------------------
@@ -356,10 +360,11 @@ template <typename T, int M>
 __global__ void __launch_bounds__(kPass2Lanes)
 single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restrict__ out) {
   __shared__ double sh_s[kPass2Lanes / 64], sh_e[kPass2Lanes / 64];
+  constexpr int P = pass2_mode(M);
   double qs = 0.0, qe = 0.0;
-  combine_strided<M>(reinterpret_cast<const double2*>(part) + static_cast<int64_t>(blockIdx.x) * nparts,
+  combine_strided<P>(reinterpret_cast<const double2*>(part) + static_cast<int64_t>(blockIdx.x) * nparts,
                      nparts, threadIdx.x, kPass2Lanes, qs, qe);
-  wave_combine<M>(qs, qe);
+  wave_combine<P>(qs, qe);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) {
     sh_s[wave] = qs;
@@ -368,7 +373,7 @@ single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restric
   __syncthreads();
   if (threadIdx.x == 0) {
     double V = sh_s[0], E = sh_e[0];
-    for (int w = 1; w < kPass2Lanes / 64; w++) combine<M>(V, E, sh_s[w], sh_e[w]);
+    for (int w = 1; w < kPass2Lanes / 64; w++) combine<P>(V, E, sh_s[w], sh_e[w]);
     finalize_store<T, M>(out, blockIdx.x, V, E);
   }
 }
@@ -695,9 +700,10 @@ seg_pass2_kernel(const int64_t* __restrict__ tbase, int64_t nseg,
     if (lane == 0) finalize_store<T, M>(out, sg, 0.0, 0.0);
     return;
   }
+  constexpr int P = pass2_mode(M);
   double qs = 0.0, qe = 0.0;
-  combine_strided<M>(reinterpret_cast<const double2*>(slots) + tb, ntl, lane, 64, qs, qe);
-  wave_combine<M>(qs, qe);
+  combine_strided<P>(reinterpret_cast<const double2*>(slots) + tb, ntl, lane, 64, qs, qe);
+  wave_combine<P>(qs, qe);
   if (lane == 0) finalize_store<T, M>(out, sg, qs, qe);
 }
 

@@ -146,6 +146,10 @@ int compute_by_mode(int mode, const void* seed, int64_t iters, const twofold_lau
         return launch_compute<T, double, kWide, DOT>(seed, iters, lc, sink, st);
       else
         return launch_compute<T, double, kDoubleDouble, DOT>(seed, iters, lc, sink, st);
+    case kMixed:
+      if constexpr (sizeof(T) == 4)
+        return launch_compute<T, double, kMixed, DOT>(seed, iters, lc, sink, st);
+      return TWOFOLD_EINVAL;
     default: return TWOFOLD_EINVAL;
   }
 }

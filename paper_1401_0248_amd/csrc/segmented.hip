@@ -115,6 +115,9 @@ int seg_by_mode(int mode, const T* x, const T* y, const int64_t* off, int64_t ns
         TWOFOLD_SEG_MODE(double, kWide);
       else
         TWOFOLD_SEG_MODE(double, kDoubleDouble);
+    case kMixed:
+      if constexpr (sizeof(T) == 4) TWOFOLD_SEG_MODE(double, kMixed);
+      return TWOFOLD_EINVAL;
     default: return TWOFOLD_EINVAL;
   }
 #undef TWOFOLD_SEG_MODE
@@ -129,7 +132,9 @@ int seg_entry(const T* x, const T* y, int64_t n_total, const int64_t* off, int64
     return TWOFOLD_EINVAL;
   // binary64 results of binary32 data (wide) go through a plan, whose output
   // is untyped; for binary64 data the wide (double-word) pairs fit out
-  if (!mode_ok(dtype, DOT, mode) || (mode == kWide && dtype == 4)) return TWOFOLD_EINVAL;
+  // binary64 results of binary32 data (wide, mixed): through a plan
+  if (!mode_ok(dtype, DOT, mode) || ((mode == kWide || mode == kMixed) && dtype == 4))
+    return TWOFOLD_EINVAL;
   if (!elem_aligned(x, dtype) || (DOT && !elem_aligned(y, dtype)) || !elem_aligned(out, dtype) ||
       !elem_aligned(off, 8))
     return TWOFOLD_EALIGN;

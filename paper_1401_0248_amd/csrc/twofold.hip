@@ -63,6 +63,9 @@ int single_by_mode(int mode, const T* x, const T* y, int64_t n, const twofold_la
         return launch_single<T, double, kWide, DOT>(x, y, n, lc, part, out, st);
       else
         return launch_single<T, double, kDoubleDouble, DOT>(x, y, n, lc, part, out, st);
+    case kMixed:
+      if constexpr (sizeof(T) == 4) return launch_single<T, double, kMixed, DOT>(x, y, n, lc, part, out, st);
+      return TWOFOLD_EINVAL;
     default: return TWOFOLD_EINVAL;
   }
 }
@@ -164,7 +167,8 @@ int multi_entry(const T* const* x, const T* const* y, const int64_t* n, int64_t 
   const int dtype = int(sizeof(T));
   if (count < 0 || count > kMaxMulti || !out) return TWOFOLD_EINVAL;
   if (count > 0 && (!x || !n || (DOT && !y))) return TWOFOLD_EINVAL;
-  if (!mode_ok(dtype, DOT, mode) || mode == kWide) return TWOFOLD_EINVAL;
+  // binary64 results (wide, mixed): one sumd/dotd or mixed call per vector
+  if (!mode_ok(dtype, DOT, mode) || mode == kWide || mode == kMixed) return TWOFOLD_EINVAL;
   if (!elem_aligned(out, dtype)) return TWOFOLD_EALIGN;
   MultiArgs<T> a;
   bool yv = true;
@@ -218,7 +222,8 @@ size_t twofold_workspace_bytes_single(int dtype, int is_dot, int mode, int64_t n
 
 int twofold_sum_f32(const float* x, int64_t n, int mode, const twofold_launch_t* launch,
                     twofold_f32_t* out, void* ws, size_t ws_bytes, void* stream) {
-  if (mode == kWide) return TWOFOLD_EINVAL;  // binary64 result: twofold_sumd_f32
+  // binary64 results: twofold_sumd_f32, twofold_sum_mixed_f32
+  if (mode == kWide || mode == kMixed) return TWOFOLD_EINVAL;
   return single_entry<float, false>(x, nullptr, n, mode, launch, out, ws, ws_bytes, stream);
 }
 int twofold_sum_f64(const double* x, int64_t n, int mode, const twofold_launch_t* launch,
@@ -229,7 +234,8 @@ int twofold_sum_f64(const double* x, int64_t n, int mode, const twofold_launch_t
 int twofold_dot_f32(const float* x, const float* y, int64_t n, int mode,
                     const twofold_launch_t* launch, twofold_f32_t* out, void* ws, size_t ws_bytes,
                     void* stream) {
-  if (mode == kWide) return TWOFOLD_EINVAL;  // binary64 result: twofold_dotd_f32
+  // binary64 results: twofold_dotd_f32, twofold_dot_mixed_f32
+  if (mode == kWide || mode == kMixed) return TWOFOLD_EINVAL;
   return single_entry<float, true>(x, y, n, mode, launch, out, ws, ws_bytes, stream);
 }
 int twofold_dot_f64(const double* x, const double* y, int64_t n, int mode,
@@ -246,6 +252,15 @@ int twofold_dotd_f32(const float* x, const float* y, int64_t n, const twofold_la
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
   return single_entry<float, true>(x, y, n, kWide, launch, out, ws, ws_bytes, stream);
 }
+int twofold_sum_mixed_f32(const float* x, int64_t n, const twofold_launch_t* launch,
+                          twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
+  return single_entry<float, false>(x, nullptr, n, kMixed, launch, out, ws, ws_bytes, stream);
+}
+int twofold_dot_mixed_f32(const float* x, const float* y, int64_t n,
+                          const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                          size_t ws_bytes, void* stream) {
+  return single_entry<float, true>(x, y, n, kMixed, launch, out, ws, ws_bytes, stream);
+}
 int twofold_sumd_f64(const double* x, int64_t n, const twofold_launch_t* launch,
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
   return single_entry<double, false>(x, nullptr, n, kWide, launch, out, ws, ws_bytes, stream);
@@ -258,7 +273,7 @@ int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_
 size_t twofold_workspace_bytes_multi(int dtype, int is_dot, int mode, const int64_t* n,
                                      int64_t count, const twofold_launch_t* launch) {
   if (!valid_dtype(dtype) || count < 0 || count > kMaxMulti || (count > 0 && !n) ||
-      !mode_ok(dtype, is_dot != 0, mode) || mode == kWide)
+      !mode_ok(dtype, is_dot != 0, mode) || mode == kWide || mode == kMixed)
     return 0;
   for (int64_t v = 0; v < count; v++)
     if (!valid_count(n[v])) return 0;

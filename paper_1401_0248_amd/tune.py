@@ -36,14 +36,15 @@ if ROOT not in sys.path:
 import paper_1401_0248_amd as tf  # noqa: E402
 
 MODES = {0: "plain", 1: "fast", 2: "rigorous", 3: "wide", 4: "kahan", 5: "fast_rounded",
-         6: "rigorous_rounded"}
+         6: "rigorous_rounded", 7: "mixed"}
 # (dtype, is_dot, mode): every form of the library (wide is binary64 for
 # binary32 data and double-word for binary64 data); the rounded-product
-# forms are dots only
+# forms are dots only, the mixed form binary32 only
 COMBOS = [(4, 0, 0), (4, 0, 1), (4, 0, 2), (4, 0, 3), (4, 0, 4),
           (8, 0, 0), (8, 0, 1), (8, 0, 2), (8, 0, 3), (8, 0, 4),
           (4, 1, 0), (4, 1, 1), (4, 1, 2), (4, 1, 3), (4, 1, 4), (4, 1, 5), (4, 1, 6),
-          (8, 1, 0), (8, 1, 1), (8, 1, 2), (8, 1, 3), (8, 1, 4), (8, 1, 5), (8, 1, 6)]
+          (8, 1, 0), (8, 1, 1), (8, 1, 2), (8, 1, 3), (8, 1, 4), (8, 1, 5), (8, 1, 6),
+          (4, 0, 7), (4, 1, 7)]
 INT64_MAX = "INT64_MAX"
 
 
@@ -110,9 +111,12 @@ def tune_single(dev, quick, combos):
                 def calls():
                     for r in range(reps):
                         x, y = xs[r % copies], ys[r % copies]
-                        o = outs[r] if (dtype == 8 or mode == 3) else outs[r].view(torch.float32)[:2]
+                        o = outs[r] if (dtype == 8 or mode in (3, 7)) else outs[r].view(torch.float32)[:2]
                         if mode == 3:
                             (tf.dotd(x, y, lc, out=o, ws=ws) if is_dot else tf.sumd(x, lc, out=o, ws=ws))
+                        elif mode == 7:
+                            (tf.dot_mixed(x, y, lc, out=o, ws=ws) if is_dot
+                             else tf.sum_mixed(x, lc, out=o, ws=ws))
                         elif is_dot:
                             tf.dot(x, y, MODES[mode], lc, out=o, ws=ws)
                         else:

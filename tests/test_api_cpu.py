@@ -69,7 +69,7 @@ def test_single_argument_checks():
     # null pointers, negative n, bad modes
     assert L.twofold_sum_f32(None, 10, 2, None, fake, ws, big, None) == EINVAL
     assert L.twofold_sum_f32(fake, -1, 2, None, fake, ws, big, None) == EINVAL
-    assert L.twofold_sum_f32(fake, 10, 7, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_sum_f32(fake, 10, 9, None, fake, ws, big, None) == EINVAL  # no such mode
     assert L.twofold_sum_f32(fake, 10, 3, None, fake, ws, big, None) == EINVAL  # wide: use sumd
     assert L.twofold_sum_f64(fake, 10, 3, None, fake, ws, big, None) == EINVAL  # wide: use sumd
     assert L.twofold_dot_f64(fake, fake, 10, 3, None, fake, ws, big, None) == EINVAL
@@ -155,8 +155,10 @@ def test_plan_rejects_bad_offsets_before_any_hip_call():
     a = np.array([0, 5], dtype=np.int64)
     assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 8, 0, 5, None,
                                      ctypes.byref(h)) == EINVAL  # rounded forms: dots only
-    assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 8, 1, 7, None,
+    assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 8, 1, 9, None,
                                      ctypes.byref(h)) == EINVAL  # no such mode
+    assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 8, 1, 7, None,
+                                     ctypes.byref(h)) == EINVAL  # mixed: binary32 only
     assert L.twofold_seg_plan_create(None, 1, 4, 0, 2, None, ctypes.byref(h)) == EINVAL
     a = np.array([0, 1 << 60], dtype=np.int64)
     assert L.twofold_seg_plan_create(ctypes.c_void_p(a.ctypes.data), 1, 4, 0, 2, None,
@@ -175,6 +177,7 @@ def test_probe_argument_checks():
                                 None) == EALIGN
     assert L.twofold_probe_read(fake, None, 160, None, fake, None) == EINVAL
     assert L.twofold_probe_compute(8, 0, 5, fake, 10, ctypes.byref(lc), fake, None) == EINVAL
+    assert L.twofold_probe_compute(8, 1, 9, fake, 10, ctypes.byref(lc), fake, None) == EINVAL
     assert L.twofold_probe_compute(8, 1, 7, fake, 10, ctypes.byref(lc), fake, None) == EINVAL
 
 
@@ -217,3 +220,34 @@ def test_multi_argument_checks():
         EWORKSPACE
     assert L.twofold_workspace_bytes_multi(8, 1, 3, long_ns, 3, None) == 0  # wide
     assert L.twofold_workspace_bytes_multi(8, 1, 2, long_ns, 65, None) == 0
+
+
+def test_mixed_mode_argument_checks():
+    """The mixed form (mode 7) exists for binary32 data only and returns
+    binary64 pairs: only twofold_{sum,dot}_mixed_f32 and plans take it."""
+    L = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 20
+    assert L.twofold_sum_f32(fake, 10, 7, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_dot_f32(fake, fake, 10, 7, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_sum_f64(fake, 10, 7, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_dot_f64(fake, fake, 10, 7, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_segsum_f32(fake, 10, fake, 3, 7, None, fake, ws, big, None) == EINVAL
+    P = ctypes.c_void_p * 1
+    N1 = ctypes.c_int64 * 1
+    assert L.twofold_multisum_f32(P(0x10000), N1(10), 1, 7, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_workspace_bytes_multi(4, 0, 7, N1(10), 1, None) == 0
+    assert L.twofold_workspace_bytes_single(8, 0, 7, 100, None) == 0
+    assert L.twofold_workspace_bytes_single(4, 1, 7, 1 << 24, None) > 0
+    lc = Launch()
+    assert L.twofold_default_launch(0, 4, 1, 7, 1 << 24, 0, ctypes.byref(lc)) == 0
+    assert L.twofold_default_launch(0, 8, 1, 7, 1 << 24, 0, ctypes.byref(lc)) == EINVAL
+    # the mixed entry points check like the others, before any HIP call
+    assert L.twofold_sum_mixed_f32(None, 10, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_dot_mixed_f32(fake, None, 10, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_sum_mixed_f32(ctypes.c_void_p(0x10002), 10, None, fake, ws, big,
+                                   None) == EALIGN
+    assert L.twofold_dot_mixed_f32(fake, fake, 10, None, ctypes.c_void_p(0x10004), ws, big,
+                                   None) == EALIGN  # binary64 output pair
+    assert L.twofold_sum_mixed_f32(fake, 1 << 24, None, fake, ws, 256, None) == EWORKSPACE
