@@ -60,6 +60,8 @@ def gpu_results(dev_in, tf):
         for mode in ("plain", "fast", "rigorous"):
             res[k + (mode,)] = tf.dot(xd, yd, mode).double().cpu().numpy()
         res[k + ("dotd",)] = tf.dotd(xd, yd).cpu().numpy()
+        if k[0] == np.float32:
+            res[k + ("mixed",)] = tf.dot_mixed(xd, yd).cpu().numpy()
     return res
 
 
@@ -143,6 +145,8 @@ def oracle_leg(host, gpu, launches, perm_host=None, perm_gpu=None):
         p = gpu[(dt, d, "dotd")]
         if dt == np.float32:
             rows.setdefault("f32data_f64plain", []).append(abs(ex.diff(p[0])) / ex.A)
+            p = gpu[(dt, d, "mixed")]
+            rows.setdefault("f32_mixed", []).append(abs(ex.diff(p[0], p[1])) / ex.A)
         else:
             rows.setdefault("f64_double_word", []).append(abs(ex.diff(p[0], p[1])) / ex.A)
         rows.setdefault("cond_" + key, []).append(2 * ex.A / abs(ex.S) if ex.S else float("inf"))
@@ -158,6 +162,9 @@ def oracle_leg(host, gpu, launches, perm_host=None, perm_gpu=None):
             p = perm_gpu[(dt, "dotd")]
             pr["f32data_f64plain" if dt == np.float32 else "f64_double_word"] = float(
                 "%.3g" % (abs(ex.diff(p[0], p[1])) / ex.A))
+            if dt == np.float32:
+                p = perm_gpu[(dt, "mixed")]
+                pr["f32_mixed"] = float("%.3g" % (abs(ex.diff(p[0], p[1])) / ex.A))
     acc = {"measure": "median over conditions of |v + e - S| / sum|x y| (*_value: |v - S| / "
                       "sum|x y|; *_q: e / (S - v); *_over_tree_bound and *_over_4Nu2_bound: the "
                       "largest |v + e - S| over the proven bound of the launch's reduction "
@@ -701,6 +708,8 @@ def main():
             for mode in ("plain", "fast", "rigorous"):
                 perm_gpu[(dt, mode)] = tf.dot(xd, yd, mode).double().cpu().numpy()
             perm_gpu[(dt, "dotd")] = tf.dotd(xd, yd).cpu().numpy()
+            if dt == np.float32:
+                perm_gpu[(dt, "mixed")] = tf.dot_mixed(xd, yd).cpu().numpy()
         res["cpu_baseline"], res["accuracy"] = oracle_leg(host, gpu, launches, perm_host, perm_gpu)
     print(json.dumps(res), flush=True)
 
