@@ -477,7 +477,10 @@ def probes(torch, tf, dev):
         W = 16 // np.dtype(dtype).itemsize
         items = bt * gb * iters * 4 * W
         for op in ("sum", "dot"):
-            for form in forms + (("fast_rounded", "rigorous_rounded") if op == "dot" else ()):
+            extra = ("fast_rounded", "rigorous_rounded") if op == "dot" else ()
+            if dtype == np.float32:
+                extra += ("mixed",)
+            for form in forms + extra:
                 t, _ = graph_time(torch, lambda: (tf.probe_compute(seed, op == "dot", form, iters,
                                                                    lc, sink), 1)[1], reps=10)
                 gelem = items / t / 1e9

@@ -193,8 +193,9 @@ int twofold_probe_compute(int dtype, int is_dot, int mode, const void* seed, int
                           const twofold_launch_t* launch, double* sink, void* stream) {
   if (!seed || !sink || iters < 0 || !launch_ok(launch)) return TWOFOLD_EINVAL;
   if (dtype != 4 && dtype != 8) return TWOFOLD_EINVAL;
-  if (mode < kPlain || mode > kRigorousRounded ||
-      ((mode == kFastRounded || mode == kRigorousRounded) && !is_dot))
+  if (mode < kPlain || mode > kMixed ||
+      ((mode == kFastRounded || mode == kRigorousRounded) && !is_dot) ||
+      (mode == kMixed && dtype != 4))
     return TWOFOLD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(seed) % uintptr_t(dtype)) || (reinterpret_cast<uintptr_t>(sink) & 7u))
     return TWOFOLD_EALIGN;

@@ -41,6 +41,8 @@ def test_compute_probe_deterministic(dtype):
         forms = ["plain", "fast", "rigorous", "kahan", "wide"]
         if is_dot:
             forms += ["fast_rounded", "rigorous_rounded"]
+        if dtype == torch.float32:
+            forms += ["mixed"]
         for form in forms:
             a = tf.probe_compute(seed, is_dot, form, 100, lc).cpu().numpy()
             b = tf.probe_compute(seed, is_dot, form, 100, lc).cpu().numpy()
