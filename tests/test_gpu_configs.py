@@ -95,17 +95,20 @@ def illcond():
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_illconditioned_bench_workload(illcond, dtype):
     u = _u(dtype)
+    devs, singles = [], {}
     for d in (6, 8, 10, 12, 14, 16):
         x, y = illcond[(dtype, d)]
         _note("ill-conditioned %s cond 1e%d" % (np.dtype(dtype).name, d))
         xd, mis = to_dev(x)
         yd, _ = to_dev(y)
+        devs.append((xd, yd))
         ex = oracle.Exact(x, y)
         for mode in ("rigorous", "fast"):
             lc, (bt, un, gb) = _bench_launch(dtype, mode, N_ILL)
             got_default = pair(tf.dot(xd, yd, mode))
             got = pair(tf.dot(xd, yd, mode, lc))
             assert same_bits(got, got_default)
+            singles[(d, mode)] = got
             want, sv = oracle.model_single(mode, x, y, mis, bt, un, gb, with_violations=True)
             assert same_bits(got, want), (d, mode, got, list(want))
             # within the bound of the launch's own tree (the fast form's
@@ -114,6 +117,16 @@ def test_illconditioned_bench_workload(illcond, dtype):
                 (d, mode, got)
             if mode == "rigorous":
                 assert abs(ex.diff(*got)) <= 4 * N_ILL * u * u * ex.A, (d, got)
+        if dtype == np.float32:
+            # the mixed form of the same data, default launch: the order
+            # model bit for bit and within the mixed tree bound
+            dl = tf.default_launch(0, 4, True, "mixed", N_ILL)
+            got = pair(tf.dot_mixed(xd, yd))
+            want = oracle.model_single("mixed", x, y, mis, dl.block_threads, dl.unroll,
+                                       dl.grid_blocks)
+            assert same_bits(got, want), (d, got, list(want))
+            Lc, D = bounds.single_depths(dtype, N_ILL, dl.block_threads, dl.unroll, dl.grid_blocks)
+            assert abs(ex.diff(*got)) <= bounds.mixed_bound(Lc, D, ex.A), (d, got)
         if dtype == np.float64:
             # the wide accumulator (double-word) of the same data, default launch
             dl = tf.default_launch(0, 8, True, "wide", N_ILL)
@@ -123,6 +136,12 @@ def test_illconditioned_bench_workload(illcond, dtype):
         # the plain value of the same launch is the twofold value
         lc, _ = _bench_launch(dtype, "rigorous", N_ILL)
         assert pair(tf.dot(xd, yd, "plain", lc))[0] == pair(tf.dot(xd, yd, "rigorous", lc))[0]
+    # the bench's step: one multi-vector call per form over the six pairs,
+    # default launch; every row is the single call's pair checked above
+    for mode in ("rigorous", "fast"):
+        out = tf.multidot([p[0] for p in devs], [p[1] for p in devs], mode)
+        for i, d in enumerate((6, 8, 10, 12, 14, 16)):
+            assert same_bits(pair(out[i]), singles[(d, mode)]), (mode, d)
 
 
 def test_one_gib_sum_f32_exact_grid():
