@@ -83,3 +83,16 @@ def test_mixed_rejects_binary64_data():
         tf.sum_mixed(x)
     with pytest.raises(tf.TwofoldError):
         tf.sum(x.float(), "mixed")
+
+
+def test_mixed_tiny_sizes():
+    e = torch.empty(0, dtype=torch.float32, device=DEV)
+    got = tf.sum_mixed(e).cpu().numpy()
+    assert got.dtype == np.float64 and np.array_equal(got.view(np.uint64), np.zeros(2, np.uint64))
+    x = torch.tensor([0.1], dtype=torch.float32, device=DEV)
+    y = torch.tensor([3.0], dtype=torch.float32, device=DEV)
+    assert pair(tf.sum_mixed(x)) == (float(np.float32(0.1)), 0.0)
+    # one product: value fl32(x*y), error its exact remainder
+    p = np.float32(0.1) * np.float32(3.0)
+    rem = float(np.float64(np.float32(0.1)) * 3.0 - np.float64(p))
+    assert pair(tf.dot_mixed(x, y)) == (float(p), rem)

@@ -123,3 +123,22 @@ def test_multi_rejects_bad_input():
         tf.multisum([x], "wide")
     with pytest.raises(tf.TwofoldError):
         tf.multidot([x[1:]], [x[:-1]], "rigorous", launch(100, 4, 1))
+
+
+def test_multi_empty_and_single_element_vectors():
+    # every vector empty: (+0, +0) each, whatever the launch
+    e = torch.empty(0, dtype=torch.float64, device="cuda:0")
+    for lc in (None, launch(256, 4, 7)):
+        out = tf.multidot([e, e, e], [e, e, e], "rigorous", lc).cpu().numpy()
+        assert np.array_equal(out.view(np.uint64), np.zeros((3, 2), dtype=np.uint64))
+    # one element each: a sum gives (x, +0), a rigorous dot (p, pi) exactly
+    xs = [torch.tensor([v], dtype=torch.float64, device="cuda:0") for v in (1.5, -2.0 ** -40, 3.0)]
+    ys = [torch.tensor([v], dtype=torch.float64, device="cuda:0") for v in (1.0 / 3, 7.0, -0.1)]
+    s = tf.multisum(xs, "rigorous").cpu().numpy()
+    assert [tuple(r) for r in s] == [(1.5, 0.0), (-2.0 ** -40, 0.0), (3.0, 0.0)]
+    d = tf.multidot(xs, ys, "rigorous").cpu().numpy()
+    for v in range(3):
+        a, b = float(xs[v][0]), float(ys[v][0])
+        p = a * b
+        pi = float(np.float64(oracle.seq("dott", np.array([a]), np.array([b]))[1]))
+        assert (d[v][0], d[v][1]) == (p, pi), v
