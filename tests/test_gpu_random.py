@@ -1,10 +1,11 @@
 """Seeded random sweep of GPU parity: every public mode and data type, sums
 and dots, sizes from 0 to about 2^18, x and y at every position inside a
-16-byte line, random launch shapes (single vector) and random batches with
+16-byte line, random launch shapes (single vector), random batches with
 empty and tiny segments, random tiles and both the device-offset and plan
-paths (segmented). Every pair must equal the order model's bit for bit.
-Also data made of signed zeros, where only the documented starting point
-(+0, +0) fixes the sign of the result."""
+paths (segmented), and random multi-vector calls (1 to 64 vectors of mixed
+lengths and alignments, explicit or default launch). Every pair must equal
+the order model's bit for bit. Also data made of signed zeros, where only
+the documented starting point (+0, +0) fixes the sign of the result."""
 import sys
 
 import numpy as np
@@ -19,7 +20,16 @@ from gpu_helpers import DEV, same_bits, to_dev
 pytestmark = pytest.mark.gpu
 
 FORMS = [(m, dot) for m in ("plain", "fast", "rigorous", "kahan") for dot in (False, True)] + \
-        [("fast_rounded", True), ("rigorous_rounded", True), ("wide", False), ("wide", True)]
+        [("fast_rounded", True), ("rigorous_rounded", True), ("wide", False), ("wide", True),
+         ("mixed", False), ("mixed", True)]
+MULTI_MODES = ("plain", "fast", "rigorous", "kahan")  # plus the rounded dots
+
+
+def _dtype_for(rng, mode):
+    """The mixed form takes binary32 data only."""
+    if mode == "mixed":
+        return np.float32
+    return (np.float32, np.float64)[rng.integers(0, 2)]
 
 
 def _note(msg):
@@ -40,6 +50,8 @@ def _values(rng, n, dtype):
 def _call(mode, dot, xd, yd, lc):
     if mode == "wide":
         return tf.dotd(xd, yd, lc) if dot else tf.sumd(xd, lc)
+    if mode == "mixed":
+        return tf.dot_mixed(xd, yd, lc) if dot else tf.sum_mixed(xd, lc)
     return tf.dot(xd, yd, mode, lc) if dot else tf.sum(xd, mode, lc)
 
 
@@ -47,8 +59,8 @@ def _call(mode, dot, xd, yd, lc):
 def test_random_single_vector(seed):
     rng = np.random.default_rng(1000 + seed)
     for case in range(40):
-        dtype = (np.float32, np.float64)[rng.integers(0, 2)]
         mode, dot = FORMS[rng.integers(0, len(FORMS))]
+        dtype = _dtype_for(rng, mode)
         W = 16 // np.dtype(dtype).itemsize
         n = int(np.floor(np.exp(rng.random() * np.log(1 << 18)))) if rng.random() < 0.9 else \
             int(rng.integers(0, 3))
@@ -70,8 +82,8 @@ def test_random_single_vector(seed):
 def test_random_segmented(seed):
     rng = np.random.default_rng(2000 + seed)
     for case in range(12):
-        dtype = (np.float32, np.float64)[rng.integers(0, 2)]
         mode, dot = FORMS[rng.integers(0, len(FORMS))]
+        dtype = _dtype_for(rng, mode)
         W = 16 // np.dtype(dtype).itemsize
         nseg = int(rng.integers(1, 400))
         lengths = np.floor(np.exp(rng.random(nseg) * np.log(1 << 14))).astype(np.int64)
@@ -96,11 +108,51 @@ def test_random_segmented(seed):
         plan.close()
         tag = (seed, case, np.dtype(dtype).name, mode, dot, nseg, ts, bt, u, gb)
         assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), tag
-        if not (mode == "wide" and dtype == np.float32):  # binary32 wide: plans only
+        if not (mode in ("wide", "mixed") and dtype == np.float32):  # these: plans only
             od = torch.from_numpy(np.asarray(off, dtype=np.int64)).to(DEV)
             dev = (tf.segdot(xd, yd, od, mode, lc) if dot else tf.segsum(xd, od, mode, lc))
             got = dev.double().cpu().numpy()
             assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), tag + ("device",)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_multi(seed):
+    rng = np.random.default_rng(3000 + seed)
+    for case in range(6):
+        dtype = (np.float32, np.float64)[rng.integers(0, 2)]
+        dot = bool(rng.integers(0, 2))
+        modes = MULTI_MODES + (("fast_rounded", "rigorous_rounded") if dot else ())
+        mode = modes[rng.integers(0, len(modes))]
+        W = 16 // np.dtype(dtype).itemsize
+        count = int(rng.integers(1, tf.MAX_MULTI + 1))
+        lengths = np.floor(np.exp(rng.random(count) * np.log(1 << 17))).astype(np.int64)
+        lengths[rng.random(count) < 0.1] = 0
+        lengths[rng.random(count) < 0.1] = 1
+        if rng.random() < 0.7:
+            bt, u, gb = int(rng.integers(1, 17)) * 64, int(rng.choice([1, 2, 4, 8])), \
+                int(rng.integers(1, 300))
+            lc = tf.Launch(bt, u, gb, 0, 0)
+        else:
+            lc = None
+            d = tf.default_launch(0, np.dtype(dtype).itemsize, dot, mode, int(lengths.max()))
+            bt, u, gb = d.block_threads, d.unroll, d.grid_blocks
+        hx, hy, dx, dy, mis = [], [], [], [], []
+        for v in range(count):
+            n = int(lengths[v])
+            x, y = _values(rng, n, dtype), _values(rng, n, dtype)
+            xd, m = to_dev(x, int(rng.integers(0, W)))
+            yd, _ = to_dev(y, int(rng.integers(0, W)))
+            hx.append(x)
+            hy.append(y)
+            dx.append(xd)
+            dy.append(yd)
+            mis.append(m)
+        out = (tf.multidot(dx, dy, mode, lc) if dot else tf.multisum(dx, mode, lc))
+        out = out.double().cpu().numpy()
+        for v in range(count):
+            want = oracle.model_single(mode, hx[v], hy[v] if dot else None, mis[v], bt, u, gb)
+            assert same_bits(tuple(out[v]), want), (seed, case, np.dtype(dtype).name, mode, dot,
+                                                    count, v, int(lengths[v]), bt, u, gb)
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
@@ -116,6 +168,8 @@ def test_signed_zeros(dtype):
         xd, mis = to_dev(x, 1)
         yd, _ = to_dev(y, 0)
         for mode, dot in FORMS:
+            if mode == "mixed" and dtype == np.float64:
+                continue
             lc = tf.Launch(128, 2, 3, 0, 0)
             got = _call(mode, dot, xd, yd, lc).double().cpu().numpy()
             want = oracle.model_single(mode, x, y if dot else None, mis, 128, 2, 3)
