@@ -10,9 +10,17 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an AMD GPU (gfx950) and the HIP library")
+    lib = os.environ.get("TWOFOLD_ORACLE_LIB")
+    if lib:
+        # the oracle's pins run against another build of it (planted-mistake
+        # copies, tests/test_oracle_mutants.py)
+        from oracle import build as oracle_build
+        oracle_build.build = lambda force=False, quiet=True: lib
 
 
 def _have_gpu():
+    if os.environ.get("TWOFOLD_ORACLE_LIB"):
+        return False  # CPU-only runs of the oracle's pins
     try:
         import torch
         return torch.cuda.is_available()

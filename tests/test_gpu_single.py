@@ -196,8 +196,8 @@ def test_workspace_needs_no_preparation():
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_subnormals_kept(dtype):
-    """Subnormal data and subnormal FMA remainders: a flush-to-zero build
-    would lose them. Compared bitwise with the order model (IEEE, no
+    """Subnormal data and subnormal FMA remainders (binary32 data also in the
+    mixed form): a flush-to-zero build would lose them. Compared bitwise with the order model (IEEE, no
     flushing) and, for the sums, exactly with the exact accumulator."""
     fi = np.finfo(dtype)
     rng = np.random.default_rng(17)
@@ -207,13 +207,14 @@ def test_subnormals_kept(dtype):
     x = np.ldexp(rng.uniform(-1, 1, n), e).astype(dtype)
     assert np.count_nonzero(np.abs(x) < fi.tiny) > n // 4
     xd, mis = to_dev(x, 1)
-    for mode in ("fast", "rigorous"):
-        got = pair(tf.sum(xd, mode, launch(256, 4, 9)))
+    for mode in ("fast", "rigorous") + (("mixed",) if dtype == np.float32 else ()):
+        lc = launch(256, 4, 9)
+        got = pair(tf.sum_mixed(xd, lc) if mode == "mixed" else tf.sum(xd, mode, lc))
         assert same_bits(got, oracle.model_single(mode, x, None, mis, 256, 4, 9)), mode
         # every round-off here is a multiple of 2^-149 small enough to be
         # held exactly, so the rigorous value + error is the exact sum (the
         # fast form can lose: t - s needs up to 26 bits on this data)
-        if mode == "rigorous":
+        if mode != "fast":
             assert oracle.Exact(x).diff(*got) == 0.0
     # dots: products near the bottom of the normal range, so their remainders
     # are subnormal
@@ -226,8 +227,9 @@ def test_subnormals_kept(dtype):
         assert np.count_nonzero((rem > 0) & (rem < float(fi.tiny))) > n // 10
     ad, mis = to_dev(a, 2)
     bd, _ = to_dev(b, 1)
-    for mode in ("fast", "rigorous", "plain"):
-        got = pair(tf.dot(ad, bd, mode, launch(512, 2, 5)))
+    for mode in ("fast", "rigorous", "plain") + (("mixed",) if dtype == np.float32 else ()):
+        lc = launch(512, 2, 5)
+        got = pair(tf.dot_mixed(ad, bd, lc) if mode == "mixed" else tf.dot(ad, bd, mode, lc))
         assert same_bits(got, oracle.model_single(mode, a, b, mis, 512, 2, 5)), mode
 
 
