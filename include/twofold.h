@@ -217,6 +217,10 @@ int twofold_dotd_f32(const float* x, const float* y, int64_t n, const twofold_la
                      twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
 /* The same for binary64 data, in double-word arithmetic (the paper's quad
  * accumulator, see above): out = (h, l), h + l the double-word sum. */
+int twofold_sumd_f64(const double* x, int64_t n, const twofold_launch_t* launch,
+                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
+int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_launch_t* launch,
+                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
 /* Mode TWOFOLD_MIXED on binary32 data (see the modes above): out->value is
  * the binary32 rigorous value, out->error the binary64 error term. */
 int twofold_sum_mixed_f32(const float* x, int64_t n, const twofold_launch_t* launch,
@@ -224,10 +228,6 @@ int twofold_sum_mixed_f32(const float* x, int64_t n, const twofold_launch_t* lau
 int twofold_dot_mixed_f32(const float* x, const float* y, int64_t n,
                           const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
                           size_t ws_bytes, void* stream);
-int twofold_sumd_f64(const double* x, int64_t n, const twofold_launch_t* launch,
-                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
-int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_launch_t* launch,
-                     twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- several vectors in one launch: count pairs into out[0..count) -------
  * x[v], y[v] (device data pointers) and n[v] (lengths) are HOST arrays of
@@ -240,10 +240,14 @@ int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_
  * ones in turn through one set. One combine kernel finishes them all, so
  * the per-call costs (kernel start and end, the combine kernel) are paid
  * once per batch.
- * Modes as the single-vector calls; TWOFOLD_WIDE and TWOFOLD_MIXED are not
- * accepted (one sumd/dotd or mixed call per vector). Workspace: twofold_workspace_bytes_multi
- * (count times the single-vector workspace of the launch); count = 0 does
- * nothing. */
+ * Modes as the single-vector calls: twofold_multisum_* / twofold_multidot_*
+ * take the modes whose results have the data's type (TWOFOLD_WIDE and
+ * TWOFOLD_MIXED give EINVAL there); the wider accumulator and the mixed form,
+ * whose results are binary64 pairs, have their own calls below, each row
+ * bitwise the matching sumd/dotd or mixed single-vector call. Workspace:
+ * twofold_workspace_bytes_multi (count times the single-vector workspace of
+ * the launch; mode TWOFOLD_WIDE or TWOFOLD_MIXED for the calls below); count
+ * = 0 does nothing. */
 size_t twofold_workspace_bytes_multi(int dtype, int is_dot, int mode, const int64_t* n,
                                      int64_t count, const twofold_launch_t* launch);
 int twofold_multisum_f32(const float* const* x, const int64_t* n, int64_t count, int mode,
@@ -258,6 +262,24 @@ int twofold_multidot_f32(const float* const* x, const float* const* y, const int
 int twofold_multidot_f64(const double* const* x, const double* const* y, const int64_t* n,
                          int64_t count, int mode, const twofold_launch_t* launch,
                          twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
+int twofold_multisumd_f32(const float* const* x, const int64_t* n, int64_t count,
+                          const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                          size_t ws_bytes, void* stream);
+int twofold_multisumd_f64(const double* const* x, const int64_t* n, int64_t count,
+                          const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                          size_t ws_bytes, void* stream);
+int twofold_multidotd_f32(const float* const* x, const float* const* y, const int64_t* n,
+                          int64_t count, const twofold_launch_t* launch, twofold_f64_t* out,
+                          void* ws, size_t ws_bytes, void* stream);
+int twofold_multidotd_f64(const double* const* x, const double* const* y, const int64_t* n,
+                          int64_t count, const twofold_launch_t* launch, twofold_f64_t* out,
+                          void* ws, size_t ws_bytes, void* stream);
+int twofold_multisum_mixed_f32(const float* const* x, const int64_t* n, int64_t count,
+                               const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                               size_t ws_bytes, void* stream);
+int twofold_multidot_mixed_f32(const float* const* x, const float* const* y, const int64_t* n,
+                               int64_t count, const twofold_launch_t* launch, twofold_f64_t* out,
+                               void* ws, size_t ws_bytes, void* stream);
 
 /* ---- segmented (CSR) batches: nseg pairs into out[0..nseg) ---------------
  * offsets: device int64[nseg + 1], non-decreasing, offsets[0] >= 0 and

@@ -183,15 +183,21 @@ def _multi(fn, xs, ys, mode, launch, out, ws):
     if need == 0:
         raise TwofoldError("twofold_workspace_bytes_multi", _lib.EINVAL)
     if out is None:
-        out = torch.empty((count, 2), dtype=xs[0].dtype, device=dev)
+        wide = m in (WIDE, MIXED)
+        out = torch.empty((count, 2), dtype=torch.float64 if wide else xs[0].dtype, device=dev)
     if ws is None:
         ws = workspace(need, dev)
     args = [ctypes.cast(xp, ctypes.c_void_p)]
     if ys is not None:
         yp = (ctypes.c_void_p * count)(*[y.data_ptr() for y in ys])
         args.append(ctypes.cast(yp, ctypes.c_void_p))
-    args += [ctypes.cast(ns, ctypes.c_void_p), count, m, lp, ctypes.c_void_p(out.data_ptr()),
-             ctypes.c_void_p(ws.ptr), ws.nbytes, _stream_ptr(dev)]
+    args.append(ctypes.cast(ns, ctypes.c_void_p))
+    args.append(count)
+    if not fn.startswith(("twofold_multisumd_", "twofold_multidotd_", "twofold_multisum_mixed_",
+                          "twofold_multidot_mixed_")):
+        args.append(m)
+    args += [lp, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.ptr), ws.nbytes,
+             _stream_ptr(dev)]
     check(fn, getattr(L, fn)(*args))
     return out
 
@@ -209,6 +215,33 @@ def multidot(xs, ys, mode="rigorous", launch=None, out=None, ws=None):
     tensor, row v bitwise the dot() of (xs[v], ys[v]) with the same launch."""
     fn = "twofold_multidot_f32" if xs[0].dtype == torch.float32 else "twofold_multidot_f64"
     return _multi(fn, xs, ys, mode, launch, out, ws)
+
+
+def multisumd(xs, launch=None, out=None, ws=None):
+    """sumd() of up to 64 vectors in one launch: a (count, 2) float64
+    tensor, row v bitwise sumd(xs[v]) with the same launch."""
+    fn = "twofold_multisumd_f32" if xs[0].dtype == torch.float32 else "twofold_multisumd_f64"
+    return _multi(fn, xs, None, WIDE, launch, out, ws)
+
+
+def multidotd(xs, ys, launch=None, out=None, ws=None):
+    """dotd() of up to 64 vector pairs in one launch (float64 rows)."""
+    fn = "twofold_multidotd_f32" if xs[0].dtype == torch.float32 else "twofold_multidotd_f64"
+    return _multi(fn, xs, ys, WIDE, launch, out, ws)
+
+
+def multisum_mixed(xs, launch=None, out=None, ws=None):
+    """sum_mixed() of up to 64 float32 vectors in one launch (float64 rows)."""
+    if xs[0].dtype != torch.float32:
+        raise TypeError("twofold: the mixed form takes float32 data")
+    return _multi("twofold_multisum_mixed_f32", xs, None, MIXED, launch, out, ws)
+
+
+def multidot_mixed(xs, ys, launch=None, out=None, ws=None):
+    """dot_mixed() of up to 64 float32 vector pairs in one launch."""
+    if xs[0].dtype != torch.float32:
+        raise TypeError("twofold: the mixed form takes float32 data")
+    return _multi("twofold_multidot_mixed_f32", xs, ys, MIXED, launch, out, ws)
 
 
 def sum_mixed(x, launch=None, out=None, ws=None):

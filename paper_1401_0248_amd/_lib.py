@@ -51,6 +51,12 @@ SIGNATURES = {
     "twofold_multisum_f64": (_int, [_vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_multidot_f32": (_int, [_vp, _vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_multidot_f64": (_int, [_vp, _vp, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_multisumd_f32": (_int, [_vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_multisumd_f64": (_int, [_vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_multidotd_f32": (_int, [_vp, _vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_multidotd_f64": (_int, [_vp, _vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_multisum_mixed_f32": (_int, [_vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_multidot_mixed_f32": (_int, [_vp, _vp, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segsum_f32": (_int, [_vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segsum_f64": (_int, [_vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segdot_f32": (_int, [_vp, _vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),

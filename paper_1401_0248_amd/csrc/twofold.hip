@@ -134,7 +134,16 @@ int multi_by_mode(int mode, const MultiArgs<T>& a, int64_t count, int sets, bool
       if constexpr (DOT)
         return launch_multi<T, T, kRigorousRounded, DOT>(a, count, sets, yv, lc, part, out, st);
       return TWOFOLD_EINVAL;
-    default: return TWOFOLD_EINVAL;  // the wider accumulator: one sumd/dotd call per vector
+    case kWide:
+      if constexpr (sizeof(T) == 4)
+        return launch_multi<T, double, kWide, DOT>(a, count, sets, yv, lc, part, out, st);
+      else
+        return launch_multi<T, double, kDoubleDouble, DOT>(a, count, sets, yv, lc, part, out, st);
+    case kMixed:
+      if constexpr (sizeof(T) == 4)
+        return launch_multi<T, double, kMixed, DOT>(a, count, sets, yv, lc, part, out, st);
+      return TWOFOLD_EINVAL;
+    default: return TWOFOLD_EINVAL;
   }
 }
 
@@ -167,9 +176,8 @@ int multi_entry(const T* const* x, const T* const* y, const int64_t* n, int64_t 
   const int dtype = int(sizeof(T));
   if (count < 0 || count > kMaxMulti || !out) return TWOFOLD_EINVAL;
   if (count > 0 && (!x || !n || (DOT && !y))) return TWOFOLD_EINVAL;
-  // binary64 results (wide, mixed): one sumd/dotd or mixed call per vector
-  if (!mode_ok(dtype, DOT, mode) || mode == kWide || mode == kMixed) return TWOFOLD_EINVAL;
-  if (!elem_aligned(out, dtype)) return TWOFOLD_EALIGN;
+  if (!mode_ok(dtype, DOT, mode)) return TWOFOLD_EINVAL;
+  if (!elem_aligned(out, out_f64(dtype, mode) ? 8 : 4)) return TWOFOLD_EALIGN;
   MultiArgs<T> a;
   bool yv = true;
   int64_t nmax = 0;
@@ -273,7 +281,7 @@ int twofold_dotd_f64(const double* x, const double* y, int64_t n, const twofold_
 size_t twofold_workspace_bytes_multi(int dtype, int is_dot, int mode, const int64_t* n,
                                      int64_t count, const twofold_launch_t* launch) {
   if (!valid_dtype(dtype) || count < 0 || count > kMaxMulti || (count > 0 && !n) ||
-      !mode_ok(dtype, is_dot != 0, mode) || mode == kWide || mode == kMixed)
+      !mode_ok(dtype, is_dot != 0, mode))
     return 0;
   for (int64_t v = 0; v < count; v++)
     if (!valid_count(n[v])) return 0;
@@ -285,22 +293,58 @@ size_t twofold_workspace_bytes_multi(int dtype, int is_dot, int mode, const int6
 int twofold_multisum_f32(const float* const* x, const int64_t* n, int64_t count, int mode,
                          const twofold_launch_t* launch, twofold_f32_t* out, void* ws,
                          size_t ws_bytes, void* stream) {
+  // binary64 results: twofold_multisumd_f32, twofold_multisum_mixed_f32
+  if (mode == kWide || mode == kMixed) return TWOFOLD_EINVAL;
   return multi_entry<float, false>(x, nullptr, n, count, mode, launch, out, ws, ws_bytes, stream);
 }
 int twofold_multisum_f64(const double* const* x, const int64_t* n, int64_t count, int mode,
                          const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
                          size_t ws_bytes, void* stream) {
+  if (mode == kWide) return TWOFOLD_EINVAL;  // the wider accumulator: twofold_multisumd_f64
   return multi_entry<double, false>(x, nullptr, n, count, mode, launch, out, ws, ws_bytes, stream);
 }
 int twofold_multidot_f32(const float* const* x, const float* const* y, const int64_t* n,
                          int64_t count, int mode, const twofold_launch_t* launch,
                          twofold_f32_t* out, void* ws, size_t ws_bytes, void* stream) {
+  // binary64 results: twofold_multidotd_f32, twofold_multidot_mixed_f32
+  if (mode == kWide || mode == kMixed) return TWOFOLD_EINVAL;
   return multi_entry<float, true>(x, y, n, count, mode, launch, out, ws, ws_bytes, stream);
 }
 int twofold_multidot_f64(const double* const* x, const double* const* y, const int64_t* n,
                          int64_t count, int mode, const twofold_launch_t* launch,
                          twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
+  if (mode == kWide) return TWOFOLD_EINVAL;  // the wider accumulator: twofold_multidotd_f64
   return multi_entry<double, true>(x, y, n, count, mode, launch, out, ws, ws_bytes, stream);
+}
+int twofold_multisumd_f32(const float* const* x, const int64_t* n, int64_t count,
+                          const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                          size_t ws_bytes, void* stream) {
+  return multi_entry<float, false>(x, nullptr, n, count, kWide, launch, out, ws, ws_bytes, stream);
+}
+int twofold_multisumd_f64(const double* const* x, const int64_t* n, int64_t count,
+                          const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                          size_t ws_bytes, void* stream) {
+  return multi_entry<double, false>(x, nullptr, n, count, kWide, launch, out, ws, ws_bytes, stream);
+}
+int twofold_multidotd_f32(const float* const* x, const float* const* y, const int64_t* n,
+                          int64_t count, const twofold_launch_t* launch, twofold_f64_t* out,
+                          void* ws, size_t ws_bytes, void* stream) {
+  return multi_entry<float, true>(x, y, n, count, kWide, launch, out, ws, ws_bytes, stream);
+}
+int twofold_multidotd_f64(const double* const* x, const double* const* y, const int64_t* n,
+                          int64_t count, const twofold_launch_t* launch, twofold_f64_t* out,
+                          void* ws, size_t ws_bytes, void* stream) {
+  return multi_entry<double, true>(x, y, n, count, kWide, launch, out, ws, ws_bytes, stream);
+}
+int twofold_multisum_mixed_f32(const float* const* x, const int64_t* n, int64_t count,
+                               const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                               size_t ws_bytes, void* stream) {
+  return multi_entry<float, false>(x, nullptr, n, count, kMixed, launch, out, ws, ws_bytes, stream);
+}
+int twofold_multidot_mixed_f32(const float* const* x, const float* const* y, const int64_t* n,
+                               int64_t count, const twofold_launch_t* launch, twofold_f64_t* out,
+                               void* ws, size_t ws_bytes, void* stream) {
+  return multi_entry<float, true>(x, y, n, count, kMixed, launch, out, ws, ws_bytes, stream);
 }
 
 const char* twofold_strerror(int status) {

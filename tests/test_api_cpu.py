@@ -218,13 +218,27 @@ def test_multi_argument_checks():
     assert one > 256 and three >= 3 * (one - 255)
     assert L.twofold_multidot_f64(xs, ys, long_ns, 3, 2, None, fake, ws, three - 256, None) == \
         EWORKSPACE
-    assert L.twofold_workspace_bytes_multi(8, 1, 3, long_ns, 3, None) == 0  # wide
     assert L.twofold_workspace_bytes_multi(8, 1, 2, long_ns, 65, None) == 0
+    # the wider accumulator and the mixed form: calls of their own, binary64 rows
+    assert L.twofold_workspace_bytes_multi(8, 1, 3, long_ns, 3, None) >= 3 * 256  # double-word
+    assert L.twofold_workspace_bytes_multi(4, 0, 7, long_ns, 3, None) >= 3 * 256
+    assert L.twofold_workspace_bytes_multi(8, 0, 7, long_ns, 3, None) == 0  # mixed: binary32 only
+    assert L.twofold_multisum_f32(xs, ns, 3, 7, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_multisum_f32(xs, ns, 3, 3, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_multisumd_f32(xs, ns, 3, None, ctypes.c_void_p(0x10004), ws, big,
+                                   None) == EALIGN  # binary64 rows
+    assert L.twofold_multidot_mixed_f32(xs, None, ns, 3, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_multidotd_f64(xs, ys, ns, 65, None, fake, ws, big, None) == EINVAL
+    assert L.twofold_multisum_mixed_f32(None, None, 0, None, fake, ws, big, None) == 0
+    assert L.twofold_multidotd_f32(xs, ys, long_ns, 3, None, fake, ws,
+                                   L.twofold_workspace_bytes_multi(4, 1, 3, long_ns, 3, None) - 256,
+                                   None) == EWORKSPACE
 
 
 def test_mixed_mode_argument_checks():
     """The mixed form (mode 7) exists for binary32 data only and returns
-    binary64 pairs: only twofold_{sum,dot}_mixed_f32 and plans take it."""
+    binary64 pairs: only twofold_{sum,dot}_mixed_f32, their multi-vector
+    forms and plans take it."""
     L = _lib.load()
     fake = ctypes.c_void_p(0x10000)
     ws = ctypes.c_void_p(0x100000)
@@ -237,7 +251,8 @@ def test_mixed_mode_argument_checks():
     P = ctypes.c_void_p * 1
     N1 = ctypes.c_int64 * 1
     assert L.twofold_multisum_f32(P(0x10000), N1(10), 1, 7, None, fake, ws, big, None) == EINVAL
-    assert L.twofold_workspace_bytes_multi(4, 0, 7, N1(10), 1, None) == 0
+    assert L.twofold_workspace_bytes_multi(4, 0, 7, N1(10), 1, None) > 0
+    assert L.twofold_workspace_bytes_multi(8, 0, 7, N1(10), 1, None) == 0
     assert L.twofold_workspace_bytes_single(8, 0, 7, 100, None) == 0
     assert L.twofold_workspace_bytes_single(4, 1, 7, 1 << 24, None) > 0
     lc = Launch()

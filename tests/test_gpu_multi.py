@@ -1,5 +1,6 @@
 """GPU parity of the multi-vector calls (twofold_multisum_* /
-twofold_multidot_*): every row is bitwise the order model's single-vector
+twofold_multidot_*, and the binary64-result forms twofold_multisumd_*,
+twofold_multidotd_*, twofold_multi{sum,dot}_mixed_f32): every row is bitwise the order model's single-vector
 result for that vector under the call's launch, and bitwise the
 single-vector call with the same launch, whatever the other vectors' lengths
 and alignments, and whether the vectors run side by side (short ones) or
@@ -90,6 +91,52 @@ def test_multi_equals_single_calls_default_launch(dtype, is_dot, longest):
             assert torch.equal(out[v].view(torch.int8), one.view(torch.int8)), (mode, v)
 
 
+def _wide_call(form, dx, dy, lc=None):
+    if form == "wide":
+        return tf.multidotd(dx, dy, lc) if dy is not None else tf.multisumd(dx, lc)
+    return tf.multidot_mixed(dx, dy, lc) if dy is not None else tf.multisum_mixed(dx, lc)
+
+
+def _wide_single(form, x, y, lc):
+    if form == "wide":
+        return tf.dotd(x, y, lc) if y is not None else tf.sumd(x, lc)
+    return tf.dot_mixed(x, y, lc) if y is not None else tf.sum_mixed(x, lc)
+
+
+@pytest.mark.parametrize("dtype,form", [(np.float32, "wide"), (np.float64, "wide"),
+                                        (np.float32, "mixed")])
+@pytest.mark.parametrize("is_dot", [False, True])
+def test_multi_wide_and_mixed_vs_model(dtype, form, is_dot):
+    """The binary64-result forms (binary64 accumulator for binary32 data,
+    double-word for binary64 data, the mixed form): every row bitwise the
+    order model's and the single-vector call's under the same launch."""
+    hx, hy, dx, dy, mis = _vectors(dtype, is_dot, LENGTHS, 500)
+    for bt, u, gb in LAUNCHES[::2] + [LAUNCHES[1]]:
+        lc = launch(bt, u, gb)
+        out = _wide_call(form, dx, dy, lc)
+        assert out.dtype == torch.float64
+        got = out.cpu().numpy()
+        for v in range(len(LENGTHS)):
+            want = oracle.model_single(form, hx[v], hy[v] if is_dot else None, mis[v], bt, u, gb)
+            assert same_bits(tuple(got[v]), want), (v, LENGTHS[v], bt, u, gb)
+            one = _wide_single(form, dx[v], dy[v] if is_dot else None, lc)
+            assert torch.equal(out[v].view(torch.int8), one.view(torch.int8)), v
+
+
+@pytest.mark.parametrize("dtype,form", [(np.float32, "wide"), (np.float64, "wide"),
+                                        (np.float32, "mixed")])
+def test_multi_wide_and_mixed_default_launch(dtype, form):
+    # long vectors in turn (2^24 + 9 binary64 elements read more than 64 MiB)
+    # and short ones side by side, each against its single call
+    for lengths in ([(1 << 24) + 9, 12345, 0, 1 << 20], [(1 << 20) + 3, 1000, 1 << 19]):
+        _, _, dx, dy, _ = _vectors(dtype, True, lengths, 600)
+        out = _wide_call(form, dx, dy)
+        lc = tf.default_launch(0, np.dtype(dtype).itemsize, True, form, max(lengths))
+        for v in range(len(lengths)):
+            one = _wide_single(form, dx[v], dy[v], lc)
+            assert torch.equal(out[v].view(torch.int8), one.view(torch.int8)), (lengths, v)
+
+
 def test_multi_64_vectors_and_graph_replay():
     lengths = [(v * 7919) % 5000 for v in range(64)]
     hx, hy, dx, dy, mis = _vectors(np.float64, True, lengths, 400)
@@ -120,7 +167,11 @@ def test_multi_rejects_bad_input():
     with pytest.raises(ValueError):
         tf.multisum([x, x.double()])
     with pytest.raises(tf.TwofoldError):
-        tf.multisum([x], "wide")
+        tf.multisum([x], "wide")  # binary64 rows: multisumd
+    with pytest.raises(tf.TwofoldError):
+        tf.multisum([x], "mixed")  # binary64 rows: multisum_mixed
+    with pytest.raises(TypeError):
+        tf.multisum_mixed([x.double()])
     with pytest.raises(tf.TwofoldError):
         tf.multidot([x[1:]], [x[:-1]], "rigorous", launch(100, 4, 1))
 

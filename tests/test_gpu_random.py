@@ -121,7 +121,8 @@ def test_random_multi(seed):
     for case in range(6):
         dtype = (np.float32, np.float64)[rng.integers(0, 2)]
         dot = bool(rng.integers(0, 2))
-        modes = MULTI_MODES + (("fast_rounded", "rigorous_rounded") if dot else ())
+        modes = MULTI_MODES + (("fast_rounded", "rigorous_rounded") if dot else ()) + ("wide",) + \
+            (("mixed",) if dtype == np.float32 else ())
         mode = modes[rng.integers(0, len(modes))]
         W = 16 // np.dtype(dtype).itemsize
         count = int(rng.integers(1, tf.MAX_MULTI + 1))
@@ -147,7 +148,12 @@ def test_random_multi(seed):
             dx.append(xd)
             dy.append(yd)
             mis.append(m)
-        out = (tf.multidot(dx, dy, mode, lc) if dot else tf.multisum(dx, mode, lc))
+        if mode == "wide":
+            out = tf.multidotd(dx, dy, lc) if dot else tf.multisumd(dx, lc)
+        elif mode == "mixed":
+            out = tf.multidot_mixed(dx, dy, lc) if dot else tf.multisum_mixed(dx, lc)
+        else:
+            out = tf.multidot(dx, dy, mode, lc) if dot else tf.multisum(dx, mode, lc)
         out = out.double().cpu().numpy()
         for v in range(count):
             want = oracle.model_single(mode, hx[v], hy[v] if dot else None, mis[v], bt, u, gb)
