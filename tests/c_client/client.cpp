@@ -95,6 +95,21 @@ int main(void) {
   HIP_OK(hipMalloc(&mws, mwsb));
   HIP_OK(hipMalloc((void**)&outm, sizeof(twofold_f64_t) * 3));
   const int rcm = twofold_multidot_f64(mx, my, mn, 3, TWOFOLD_RIGOROUS, NULL, outm, mws, mwsb, st);
+
+  // binary64 results: the mixed-form dot of xf with itself, and double-word
+  // sums of x and of x from element 1 on in one multi-vector call
+  const double* wx[2] = {x, x + 1};
+  const int64_t wn[2] = {kN, kN - 1};
+  size_t xwsb = twofold_workspace_bytes_single(4, 1, TWOFOLD_MIXED, kN, NULL);
+  size_t w4 = twofold_workspace_bytes_multi(8, 0, TWOFOLD_WIDE, wn, 2, NULL);
+  if (w4 > xwsb) xwsb = w4;
+  void* xws;
+  twofold_f64_t* outw;
+  HIP_OK(hipMalloc(&xws, xwsb));
+  HIP_OK(hipMalloc((void**)&outw, sizeof(twofold_f64_t) * 3));
+  const int rcx = twofold_dot_mixed_f32(xf, xf, kN, NULL, &outw[0], xws, xwsb, st);
+  // the same workspace: calls on one stream run in order
+  const int rcw = twofold_multisumd_f64(wx, wn, 2, NULL, &outw[1], xws, xwsb, st);
   HIP_OK(hipStreamSynchronize(st));
 
   twofold_f64_t r64[8];
@@ -118,6 +133,11 @@ int main(void) {
   HIP_OK(hipMemcpy(rm, outm, sizeof(rm), hipMemcpyDeviceToHost));
   for (int v = 0; v < 3; v++)
     printf("multidot_f64_rigorous_%d %d %a %a\n", v, rcm, rm[v].value, rm[v].error);
+  twofold_f64_t rw[3];
+  HIP_OK(hipMemcpy(rw, outw, sizeof(rw), hipMemcpyDeviceToHost));
+  printf("dot_mixed_f32 %d %a %a\n", rcx, rw[0].value, rw[0].error);
+  for (int v = 0; v < 2; v++)
+    printf("multisumd_f64_%d %d %a %a\n", v, rcw, rw[1 + v].value, rw[1 + v].error);
 
   HIP_OK(hipFree(x));
   HIP_OK(hipFree(y));
@@ -131,6 +151,8 @@ int main(void) {
   HIP_OK(hipFree(nflag));
   HIP_OK(hipFree(mws));
   HIP_OK(hipFree(outm));
+  HIP_OK(hipFree(xws));
+  HIP_OK(hipFree(outw));
   if (plan) twofold_seg_plan_destroy(plan);
   HIP_OK(hipStreamDestroy(st));
   free(hx);

@@ -83,6 +83,15 @@ def test_native_client_matches_the_oracle():
         want = oracle.model_single("rigorous", x[a:a + n], y[a:a + n], a % 2, lc.block_threads,
                                    lc.unroll, lc.grid_blocks)
         assert _pair(rows["multidot_f64_rigorous_%d" % v]) == (want[0], want[1]), v
+    # binary64 results: the mixed-form dot, double-word sums in one call
+    lc = _launch(0, 4, 1, 7, N)
+    want = oracle.model_single("mixed", xf, xf, mis, lc.block_threads, lc.unroll, lc.grid_blocks)
+    assert _pair(rows["dot_mixed_f32"]) == (want[0], want[1])
+    lc = _launch(0, 8, 0, 3, N)
+    for v, a in enumerate((0, 1)):
+        want = oracle.model_single("wide", x[a:], None, a % 2, lc.block_threads, lc.unroll,
+                                   lc.grid_blocks)
+        assert _pair(rows["multisumd_f64_%d" % v]) == (want[0], want[1]), v
     m = rows["monitor"]
     assert int(m[0]) == 0
     flags = monitor.flags(seg, np.diff(OFF), 0.0, np.float64)
