@@ -16,9 +16,13 @@ The tuned values change result bits (the reduction order depends on the
 launch), so the table is checked in and changed only by re-running this.
 
 Usage: python -m paper_1401_0248_amd.tune --out tuned_table.inc [--quick]
-       [--only single|seg] [--combo DTYPE,IS_DOT,MODE ...]
-With --combo only those combinations are timed, and the file holds only
-their rows, to be merged into csrc/tuned_table.inc in place of theirs.
+       [--only single|seg] [--combo DTYPE,IS_DOT,MODE ...] [--bucket N_MAX ...]
+       [--passes P]
+With --combo (or --bucket) only those combinations (size buckets) are
+timed, and the file holds only their rows, to be merged into
+csrc/tuned_table.inc in place of theirs. With --passes P every
+single-vector candidate is timed P times, in alternating order, and keeps
+its best time.
 """
 import argparse
 import itertools
@@ -83,11 +87,13 @@ def single_candidates(quick):
     return list(itertools.product(bts, us, gbs))
 
 
-def tune_single(dev, quick, combos):
+def tune_single(dev, quick, combos, only_buckets=None, passes=1):
     rows = []
     # bucket upper bounds and the size timed for each
     buckets = [(1 << 14, 1 << 14), (1 << 18, 1 << 18), (1 << 22, 1 << 22), (1 << 24, 1 << 24),
                (1 << 25, 1 << 25), (INT64_MAX, None)]
+    if only_buckets:
+        buckets = [b for b in buckets if b[0] in only_buckets]
     big = {4: 1 << 28, 8: 1 << 27}  # 1 GiB per vector
     for dtype, is_dot, mode in combos:
         tdt = torch.float32 if dtype == 4 else torch.float64
@@ -102,8 +108,7 @@ def tune_single(dev, quick, combos):
                 if is_dot else [None] * copies
             reps = max(copies, min(64, (1 << 30) // (n * dtype)))
             outs = torch.empty((reps, 2), dtype=torch.float64, device=dev)
-            best = None
-            for bt, u, gb in single_candidates(quick):
+            def time_candidate(bt, u, gb):
                 lc = tf.Launch(bt, u, gb, 0, 0)
                 need = tf._lib.load().twofold_workspace_bytes_single(dtype, is_dot, mode, n, lc)
                 ws = tf.Workspace(need, dev)
@@ -123,9 +128,18 @@ def tune_single(dev, quick, combos):
                             tf.sum(x, MODES[mode], lc, out=o, ws=ws)
                     return reps
 
-                t = time_graph(calls)
-                if best is None or t < best[0]:
-                    best = (t, bt, u, gb)
+                return time_graph(calls)
+
+            # every pass times all candidates, in alternating order; a
+            # candidate keeps its best time, so one slow replay does not
+            # decide
+            cands = single_candidates(quick)
+            times = {}
+            for p in range(passes):
+                for c in (cands if p % 2 == 0 else cands[::-1]):
+                    t = time_candidate(*c)
+                    times[c] = min(t, times.get(c, t))
+            best = min((t,) + c for c, t in times.items())
             t, bt, u, gb = best
             gbs = n * dtype * (2 if is_dot else 1) / t / 1e9
             log("single dtype=%d dot=%d %s n=%d: bt=%d u=%d max_blocks=%d  %.2f us  %.0f GB/s"
@@ -200,6 +214,11 @@ def main():
     ap.add_argument("--only", choices=("single", "seg"), default=None)
     ap.add_argument("--combo", action="append", default=None, metavar="DTYPE,IS_DOT,MODE",
                     help="tune only these combinations (repeatable), e.g. 8,1,3")
+    ap.add_argument("--bucket", action="append", default=None, metavar="N_MAX",
+                    help="single vector: tune only the size buckets with this upper bound "
+                         "(repeatable; 'max' for the last one)")
+    ap.add_argument("--passes", type=int, default=1,
+                    help="single vector: time every candidate this many times, keep its best")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     props = torch.cuda.get_device_properties(dev)
@@ -213,7 +232,10 @@ def main():
                 ap.error("unknown combination %s" % (c,))
     rows = []
     if args.only in (None, "single"):
-        rows += tune_single(dev, args.quick, combos)
+        only = None
+        if args.bucket:
+            only = [INT64_MAX if b == "max" else int(b) for b in args.bucket]
+        rows += tune_single(dev, args.quick, combos, only, max(1, args.passes))
     if args.only in (None, "seg"):
         rows += tune_seg(dev, args.quick, combos)
     with open(args.out, "w") as f:
