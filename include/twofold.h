@@ -285,8 +285,12 @@ int twofold_multidot_mixed_f32(const float* const* x, const float* const* y, con
  * offsets: device int64[nseg + 1], non-decreasing, offsets[0] >= 0 and
  * offsets[nseg] <= n_total (the length of x and y). Checked on the device:
  * on violation every out[s] is NaN.
- * mode TWOFOLD_WIDE is accepted here for binary64 data only, and
- * TWOFOLD_MIXED not at all (binary32 data: see the plan interface). */
+ * twofold_segsum_f32 / twofold_segdot_f32 take the modes with binary32
+ * results (TWOFOLD_WIDE and TWOFOLD_MIXED give EINVAL there); the _f64 calls
+ * also take TWOFOLD_WIDE (double-word pairs). The binary64-result forms have
+ * their own calls below: the wider accumulator (segsumd / segdotd, both
+ * data types; for binary64 data the same as mode TWOFOLD_WIDE) and the
+ * mixed form (binary32 data), out = binary64 pairs. */
 int twofold_segsum_f32(const float* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
                        int mode, const twofold_launch_t* launch, twofold_f32_t* out, void* ws,
                        size_t ws_bytes, void* stream);
@@ -299,6 +303,24 @@ int twofold_segdot_f32(const float* x, const float* y, int64_t n_total, const in
 int twofold_segdot_f64(const double* x, const double* y, int64_t n_total, const int64_t* offsets,
                        int64_t nseg, int mode, const twofold_launch_t* launch, twofold_f64_t* out,
                        void* ws, size_t ws_bytes, void* stream);
+int twofold_segsumd_f32(const float* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
+                        const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                        size_t ws_bytes, void* stream);
+int twofold_segsumd_f64(const double* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
+                        const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                        size_t ws_bytes, void* stream);
+int twofold_segdotd_f32(const float* x, const float* y, int64_t n_total, const int64_t* offsets,
+                        int64_t nseg, const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                        size_t ws_bytes, void* stream);
+int twofold_segdotd_f64(const double* x, const double* y, int64_t n_total, const int64_t* offsets,
+                        int64_t nseg, const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                        size_t ws_bytes, void* stream);
+int twofold_segsum_mixed_f32(const float* x, int64_t n_total, const int64_t* offsets,
+                             int64_t nseg, const twofold_launch_t* launch, twofold_f64_t* out,
+                             void* ws, size_t ws_bytes, void* stream);
+int twofold_segdot_mixed_f32(const float* x, const float* y, int64_t n_total,
+                             const int64_t* offsets, int64_t nseg, const twofold_launch_t* launch,
+                             twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- segmented plans: host offsets fixed once, one kernel per execute ---
  * create: validates offsets_host (host int64[nseg+1], offsets[0] = 0,

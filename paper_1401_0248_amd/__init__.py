@@ -259,7 +259,7 @@ def dot_mixed(x, y, launch=None, out=None, ws=None):
     return _single("twofold_dot_mixed_f32", x, y, MIXED, launch, out, ws, torch.float64)
 
 
-def _seg(x, y, offsets, mode, launch, out, ws):
+def _seg(x, y, offsets, mode, launch, out, ws, fn=None):
     L = _lib.load()
     _check_data(*([x] if y is None else [x, y]))
     if offsets.dtype != torch.int64 or offsets.device != x.device or offsets.dim() != 1 \
@@ -277,19 +277,22 @@ def _seg(x, y, offsets, mode, launch, out, ws):
     if need == 0:
         raise TwofoldError("twofold_workspace_bytes_seg", _lib.EINVAL)
     if out is None:
-        out = torch.empty((nseg, 2), dtype=x.dtype, device=dev)
+        wide = fn is not None or x.dtype == torch.float64
+        out = torch.empty((nseg, 2), dtype=torch.float64 if wide else x.dtype, device=dev)
     if ws is None:
         ws = workspace(need, dev)
     sfx = "f32" if x.dtype == torch.float32 else "f64"
-    if y is None:
-        check("twofold_segsum_" + sfx, getattr(L, "twofold_segsum_" + sfx)(
-            ctypes.c_void_p(x.data_ptr()), n_total, ctypes.c_void_p(offsets.data_ptr()), nseg, m, lp,
-            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.ptr), ws.nbytes, _stream_ptr(dev)))
+    if fn is None:  # the generic calls take the mode
+        fn = ("twofold_segsum_" if y is None else "twofold_segdot_") + sfx
+        tail = [m, lp]
     else:
-        check("twofold_segdot_" + sfx, getattr(L, "twofold_segdot_" + sfx)(
-            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), n_total,
-            ctypes.c_void_p(offsets.data_ptr()), nseg, m, lp, ctypes.c_void_p(out.data_ptr()),
-            ctypes.c_void_p(ws.ptr), ws.nbytes, _stream_ptr(dev)))
+        tail = [lp]
+    args = [ctypes.c_void_p(x.data_ptr())]
+    if y is not None:
+        args.append(ctypes.c_void_p(y.data_ptr()))
+    args += [n_total, ctypes.c_void_p(offsets.data_ptr()), nseg] + tail + \
+        [ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.ptr), ws.nbytes, _stream_ptr(dev)]
+    check(fn, getattr(L, fn)(*args))
     return out
 
 
@@ -301,6 +304,32 @@ def segsum(x, offsets, mode="rigorous", launch=None, out=None, ws=None):
 def segdot(x, y, offsets, mode="rigorous", launch=None, out=None, ws=None):
     """Twofold dot products of the CSR segments of x and y: (nseg, 2)."""
     return _seg(x, y, offsets, mode, launch, out, ws)
+
+
+def segsumd(x, offsets, launch=None, out=None, ws=None):
+    """sumd() of every CSR segment of x: (nseg, 2) float64 rows."""
+    fn = "twofold_segsumd_f32" if x.dtype == torch.float32 else "twofold_segsumd_f64"
+    return _seg(x, None, offsets, WIDE, launch, out, ws, fn)
+
+
+def segdotd(x, y, offsets, launch=None, out=None, ws=None):
+    """dotd() of every CSR segment of x and y: (nseg, 2) float64 rows."""
+    fn = "twofold_segdotd_f32" if x.dtype == torch.float32 else "twofold_segdotd_f64"
+    return _seg(x, y, offsets, WIDE, launch, out, ws, fn)
+
+
+def segsum_mixed(x, offsets, launch=None, out=None, ws=None):
+    """sum_mixed() of every CSR segment of float32 x: (nseg, 2) float64 rows."""
+    if x.dtype != torch.float32:
+        raise TypeError("twofold: the mixed form takes float32 data")
+    return _seg(x, None, offsets, MIXED, launch, out, ws, "twofold_segsum_mixed_f32")
+
+
+def segdot_mixed(x, y, offsets, launch=None, out=None, ws=None):
+    """dot_mixed() of every CSR segment of float32 x and y (float64 rows)."""
+    if x.dtype != torch.float32:
+        raise TypeError("twofold: the mixed form takes float32 data")
+    return _seg(x, y, offsets, MIXED, launch, out, ws, "twofold_segdot_mixed_f32")
 
 
 class SegPlan:

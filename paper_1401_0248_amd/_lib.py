@@ -61,6 +61,12 @@ SIGNATURES = {
     "twofold_segsum_f64": (_int, [_vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segdot_f32": (_int, [_vp, _vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
     "twofold_segdot_f64": (_int, [_vp, _vp, _i64, _vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_segsumd_f32": (_int, [_vp, _i64, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_segsumd_f64": (_int, [_vp, _i64, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_segdotd_f32": (_int, [_vp, _vp, _i64, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_segdotd_f64": (_int, [_vp, _vp, _i64, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_segsum_mixed_f32": (_int, [_vp, _i64, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
+    "twofold_segdot_mixed_f32": (_int, [_vp, _vp, _i64, _vp, _i64, _LP, _vp, _vp, _sz, _vp]),
     "twofold_seg_plan_create": (_int, [_vp, _i64, _int, _int, _int, _LP, ctypes.POINTER(_vp)]),
     "twofold_seg_plan_workspace_bytes": (_sz, [_vp]),
     "twofold_seg_plan_get_launch": (_int, [_vp, _LP]),

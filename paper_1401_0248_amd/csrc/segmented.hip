@@ -130,13 +130,9 @@ int seg_entry(const T* x, const T* y, int64_t n_total, const int64_t* off, int64
   if ((!x && n_total > 0) || !out || !off || (DOT && !y && n_total > 0) || !valid_count(n_total) ||
       !valid_count(nseg))
     return TWOFOLD_EINVAL;
-  // binary64 results of binary32 data (wide) go through a plan, whose output
-  // is untyped; for binary64 data the wide (double-word) pairs fit out
-  // binary64 results of binary32 data (wide, mixed): through a plan
-  if (!mode_ok(dtype, DOT, mode) || ((mode == kWide || mode == kMixed) && dtype == 4))
-    return TWOFOLD_EINVAL;
-  if (!elem_aligned(x, dtype) || (DOT && !elem_aligned(y, dtype)) || !elem_aligned(out, dtype) ||
-      !elem_aligned(off, 8))
+  if (!mode_ok(dtype, DOT, mode)) return TWOFOLD_EINVAL;
+  if (!elem_aligned(x, dtype) || (DOT && !elem_aligned(y, dtype)) ||
+      !elem_aligned(out, out_f64(dtype, mode) ? 8 : 4) || !elem_aligned(off, 8))
     return TWOFOLD_EALIGN;
   twofold_launch_t lc;
   const int rc = resolve_seg(dtype, DOT, mode, n_total, launch, &lc);
@@ -207,6 +203,8 @@ size_t twofold_workspace_bytes_seg(int dtype, int is_dot, int mode, int64_t n_to
 int twofold_segsum_f32(const float* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
                        int mode, const twofold_launch_t* launch, twofold_f32_t* out, void* ws,
                        size_t ws_bytes, void* stream) {
+  // binary64 results: twofold_segsumd_f32, twofold_segsum_mixed_f32
+  if (mode == kWide || mode == kMixed) return TWOFOLD_EINVAL;
   return seg_entry<float, false>(x, nullptr, n_total, offsets, nseg, mode, launch, out, ws, ws_bytes,
                                  stream);
 }
@@ -219,12 +217,50 @@ int twofold_segsum_f64(const double* x, int64_t n_total, const int64_t* offsets,
 int twofold_segdot_f32(const float* x, const float* y, int64_t n_total, const int64_t* offsets,
                        int64_t nseg, int mode, const twofold_launch_t* launch, twofold_f32_t* out,
                        void* ws, size_t ws_bytes, void* stream) {
+  // binary64 results: twofold_segdotd_f32, twofold_segdot_mixed_f32
+  if (mode == kWide || mode == kMixed) return TWOFOLD_EINVAL;
   return seg_entry<float, true>(x, y, n_total, offsets, nseg, mode, launch, out, ws, ws_bytes, stream);
 }
 int twofold_segdot_f64(const double* x, const double* y, int64_t n_total, const int64_t* offsets,
                        int64_t nseg, int mode, const twofold_launch_t* launch, twofold_f64_t* out,
                        void* ws, size_t ws_bytes, void* stream) {
   return seg_entry<double, true>(x, y, n_total, offsets, nseg, mode, launch, out, ws, ws_bytes, stream);
+}
+int twofold_segsumd_f32(const float* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
+                        const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  return seg_entry<float, false>(x, nullptr, n_total, offsets, nseg, kWide, launch, out, ws,
+                                 ws_bytes, stream);
+}
+int twofold_segsumd_f64(const double* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
+                        const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  return seg_entry<double, false>(x, nullptr, n_total, offsets, nseg, kWide, launch, out, ws,
+                                  ws_bytes, stream);
+}
+int twofold_segdotd_f32(const float* x, const float* y, int64_t n_total, const int64_t* offsets,
+                        int64_t nseg, const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  return seg_entry<float, true>(x, y, n_total, offsets, nseg, kWide, launch, out, ws, ws_bytes,
+                                stream);
+}
+int twofold_segdotd_f64(const double* x, const double* y, int64_t n_total, const int64_t* offsets,
+                        int64_t nseg, const twofold_launch_t* launch, twofold_f64_t* out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  return seg_entry<double, true>(x, y, n_total, offsets, nseg, kWide, launch, out, ws, ws_bytes,
+                                 stream);
+}
+int twofold_segsum_mixed_f32(const float* x, int64_t n_total, const int64_t* offsets,
+                             int64_t nseg, const twofold_launch_t* launch, twofold_f64_t* out,
+                             void* ws, size_t ws_bytes, void* stream) {
+  return seg_entry<float, false>(x, nullptr, n_total, offsets, nseg, kMixed, launch, out, ws,
+                                 ws_bytes, stream);
+}
+int twofold_segdot_mixed_f32(const float* x, const float* y, int64_t n_total,
+                             const int64_t* offsets, int64_t nseg, const twofold_launch_t* launch,
+                             twofold_f64_t* out, void* ws, size_t ws_bytes, void* stream) {
+  return seg_entry<float, true>(x, y, n_total, offsets, nseg, kMixed, launch, out, ws, ws_bytes,
+                                stream);
 }
 
 int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype, int is_dot,

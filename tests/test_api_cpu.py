@@ -142,6 +142,16 @@ def test_segmented_argument_checks():
     assert L.twofold_segsum_f32(fake, 10, fake, 3, 2, ctypes.byref(lc), fake, ws, 1 << 20, None) == EINVAL
     # nseg == 0: nothing to do, nothing launched
     assert L.twofold_segsum_f32(fake, 0, fake, 0, 2, None, fake, ws, 1 << 20, None) == 0
+    # binary64 rows of binary32 data: their own calls, checked the same way
+    assert L.twofold_segdot_f32(fake, fake, 10, fake, 3, 7, None, fake, ws, 1 << 20, None) == EINVAL
+    assert L.twofold_segsumd_f32(fake, 10, None, 3, None, fake, ws, 1 << 20, None) == EINVAL
+    assert L.twofold_segdot_mixed_f32(fake, None, 10, fake, 3, None, fake, ws, 1 << 20,
+                                      None) == EINVAL
+    assert L.twofold_segsum_mixed_f32(fake, 10, fake, 3, None, ctypes.c_void_p(0x10004), ws,
+                                      1 << 20, None) == EALIGN  # binary64 output pairs
+    assert L.twofold_segdotd_f64(fake, fake, 1 << 20, fake, 5000, None, fake, ws, 1024,
+                                 None) == EWORKSPACE
+    assert L.twofold_segsumd_f64(fake, 0, fake, 0, None, fake, ws, 1 << 20, None) == 0
 
 
 def test_plan_rejects_bad_offsets_before_any_hip_call():

@@ -2,7 +2,7 @@
 and dots, sizes from 0 to about 2^18, x and y at every position inside a
 16-byte line, random launch shapes (single vector), random batches with
 empty and tiny segments, random tiles and both the device-offset and plan
-paths (segmented), and random multi-vector calls (1 to 64 vectors of mixed
+paths (segmented, every mode on both), and random multi-vector calls (1 to 64 vectors of mixed
 lengths and alignments, explicit or default launch). Every pair must equal
 the order model's bit for bit. Also data made of signed zeros, where only
 the documented starting point (+0, +0) fixes the sign of the result."""
@@ -108,11 +108,15 @@ def test_random_segmented(seed):
         plan.close()
         tag = (seed, case, np.dtype(dtype).name, mode, dot, nseg, ts, bt, u, gb)
         assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), tag
-        if not (mode in ("wide", "mixed") and dtype == np.float32):  # these: plans only
-            od = torch.from_numpy(np.asarray(off, dtype=np.int64)).to(DEV)
-            dev = (tf.segdot(xd, yd, od, mode, lc) if dot else tf.segsum(xd, od, mode, lc))
-            got = dev.double().cpu().numpy()
-            assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), tag + ("device",)
+        od = torch.from_numpy(np.asarray(off, dtype=np.int64)).to(DEV)
+        if mode == "mixed":
+            dev = tf.segdot_mixed(xd, yd, od, lc) if dot else tf.segsum_mixed(xd, od, lc)
+        elif mode == "wide" and dtype == np.float32:
+            dev = tf.segdotd(xd, yd, od, lc) if dot else tf.segsumd(xd, od, lc)
+        else:
+            dev = tf.segdot(xd, yd, od, mode, lc) if dot else tf.segsum(xd, od, mode, lc)
+        got = dev.double().cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), tag + ("device",)
 
 
 @pytest.mark.parametrize("seed", range(8))

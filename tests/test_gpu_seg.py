@@ -97,6 +97,46 @@ def test_wide_plan_vs_model(dtype):
             dev = _rows(tf.segdot(xd, yd, od, "wide", lc) if is_dot else tf.segsum(xd, od, "wide", lc))
             for s in range(len(L)):
                 assert same_bits(dev[s], want[s]), s
+        # the typed device-offset calls (segsumd / segdotd), both data types
+        got_d = tf.segdotd(xd, yd, od, lc) if is_dot else tf.segsumd(xd, od, lc)
+        assert got_d.dtype == torch.float64
+        dev = _rows(got_d)
+        for s in range(len(L)):
+            assert same_bits(dev[s], want[s]), s
+
+
+@pytest.mark.parametrize("is_dot", [False, True])
+def test_mixed_device_offsets_vs_model(is_dot):
+    """The mixed form through the device-offset calls (segsum_mixed /
+    segdot_mixed): bitwise the order model's and the plan's, binary64 rows."""
+    L = _lengths()
+    off = synth.offsets_from_lengths(L)
+    n = int(off[-1])
+    rng = np.random.default_rng(8)
+    x = (rng.standard_normal(n) * np.exp2(rng.integers(-12, 12, n))).astype(np.float32)
+    y = rng.standard_normal(n).astype(np.float32)
+    od = torch.from_numpy(off).to(DEV)
+    for ts, u, gb, bt, xs, ys in ((256, 1, 1, 64, 0, 0), (1024, 4, 3, 256, 1, 2),
+                                  (4096, 8, 50, 512, 3, 3)):
+        xd, mis = to_dev(x, xs)
+        yd, _ = to_dev(y, ys)
+        lc = launch(bt, u, gb, ts)
+        got = tf.segdot_mixed(xd, yd, od, lc) if is_dot else tf.segsum_mixed(xd, od, lc)
+        assert got.dtype == torch.float64
+        want = oracle.model_seg("mixed", x, off, y if is_dot else None, mis, u, ts)
+        g = _rows(got)
+        for s in range(len(L)):
+            assert same_bits(g[s], want[s]), (s, ts, u)
+        plan = tf.SegPlan(off, torch.float32, is_dot, "mixed", lc)
+        assert torch.equal(plan.execute(xd, yd if is_dot else None), got)
+        plan.close()
+    # default launch, and the checks of the typed calls
+    got = tf.segdot_mixed(xd, yd, od) if is_dot else tf.segsum_mixed(xd, od)
+    assert torch.isfinite(got).all()
+    with pytest.raises(TypeError):
+        tf.segsum_mixed(xd.double(), od)
+    with pytest.raises(tf.TwofoldError):
+        tf.segsum(xd, od, "mixed")
 
 
 def test_invalid_device_offsets_give_nan():
