@@ -49,6 +49,18 @@ def _stream_ptr(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _out(out, rows, dtype, device, shape):
+    """The output tensor: a new one, or the caller's after checking that the
+    library's rows fit it (the library writes rows pairs of dtype)."""
+    if out is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    if not isinstance(out, torch.Tensor) or out.device != torch.device(device) or \
+            out.dtype != dtype or not out.is_contiguous() or out.numel() < 2 * rows:
+        raise ValueError("twofold: out must be a contiguous %s tensor of at least %d elements "
+                         "on %s" % (dtype, 2 * rows, device))
+    return out
+
+
 def _check_data(*ts):
     t0 = ts[0]
     if not t0.is_cuda:
@@ -111,8 +123,7 @@ def _single(fn, x, y, mode, launch, out, ws, out_dtype):
     need = L.twofold_workspace_bytes_single(dt, int(y is not None), m, n, lp)
     if need == 0:
         raise TwofoldError("twofold_workspace_bytes_single", _lib.EINVAL)
-    if out is None:
-        out = torch.empty(2, dtype=out_dtype, device=dev)
+    out = _out(out, 1, out_dtype, dev, (2,))
     if ws is None:
         ws = workspace(need, dev)
     args = [ctypes.c_void_p(x.data_ptr())]
@@ -182,9 +193,8 @@ def _multi(fn, xs, ys, mode, launch, out, ws):
                                            count, lp)
     if need == 0:
         raise TwofoldError("twofold_workspace_bytes_multi", _lib.EINVAL)
-    if out is None:
-        wide = m in (WIDE, MIXED)
-        out = torch.empty((count, 2), dtype=torch.float64 if wide else xs[0].dtype, device=dev)
+    odt = torch.float64 if m in (WIDE, MIXED) else xs[0].dtype
+    out = _out(out, count, odt, dev, (count, 2))
     if ws is None:
         ws = workspace(need, dev)
     args = [ctypes.cast(xp, ctypes.c_void_p)]
@@ -276,9 +286,8 @@ def _seg(x, y, offsets, mode, launch, out, ws, fn=None):
     need = L.twofold_workspace_bytes_seg(dt, int(y is not None), m, n_total, nseg, lp)
     if need == 0:
         raise TwofoldError("twofold_workspace_bytes_seg", _lib.EINVAL)
-    if out is None:
-        wide = fn is not None or x.dtype == torch.float64
-        out = torch.empty((nseg, 2), dtype=torch.float64 if wide else x.dtype, device=dev)
+    odt = torch.float64 if (fn is not None or x.dtype == torch.float64) else x.dtype
+    out = _out(out, nseg, odt, dev, (nseg, 2))
     if ws is None:
         ws = workspace(need, dev)
     sfx = "f32" if x.dtype == torch.float32 else "f64"
@@ -362,8 +371,7 @@ class SegPlan:
         _check_data(*([x] if y is None else [x, y]))
         if x.element_size() != self.dtype:
             raise TypeError("SegPlan: data type differs from the plan's")
-        if out is None:
-            out = torch.empty((self.nseg, 2), dtype=self.out_dtype, device=x.device)
+        out = _out(out, self.nseg, self.out_dtype, x.device, (self.nseg, 2))
         if ws is None:
             ws = workspace(self.workspace_bytes, x.device)
         if self.is_dot != (y is not None):
@@ -409,8 +417,14 @@ def monitor(pairs, tau, offsets=None, n=None, flags=None, nflagged=None):
                              "the pairs' device")
     if flags is None:
         flags = torch.empty(count, dtype=torch.int32, device=dev)
+    elif flags.device != dev or flags.element_size() != 4 or not flags.is_contiguous() or \
+            flags.numel() < count:
+        raise ValueError("flags must be a contiguous 4-byte tensor of count entries on the "
+                         "pairs' device")
     if nflagged is None:
         nflagged = torch.empty((), dtype=torch.int64, device=dev)
+    elif nflagged.device != dev or nflagged.dtype != torch.int64 or nflagged.numel() < 1:
+        raise ValueError("nflagged must be an int64 tensor on the pairs' device")
     check("twofold_monitor", L.twofold_monitor(
         pairs.element_size(), ctypes.c_void_p(pairs.data_ptr()) if count else None, count,
         ctypes.c_void_p(offsets.data_ptr()) if offsets is not None else None,
@@ -430,6 +444,9 @@ def probe_read(x, y=None, launch=None, sink=None):
     nbytes = x.numel() * x.element_size()
     if sink is None:
         sink = torch.empty(launch.grid_blocks, dtype=torch.int64, device=x.device)
+    elif sink.device != x.device or sink.element_size() != 8 or not sink.is_contiguous() or \
+            sink.numel() < launch.grid_blocks:
+        raise ValueError("sink must be a contiguous 8-byte tensor of grid_blocks entries")
     check("twofold_probe_read", L.twofold_probe_read(
         ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()) if y is not None else None,
         nbytes, ctypes.byref(launch), ctypes.c_void_p(sink.data_ptr()), _stream_ptr(x.device)))
@@ -441,9 +458,16 @@ def probe_compute(seed, is_dot, mode, iters, launch, sink=None):
     L = _lib.load()
     if isinstance(launch, dict):
         launch = Launch(**launch)
+    if not seed.is_cuda or seed.dtype not in (torch.float32, torch.float64) or \
+            not seed.is_contiguous() or seed.numel() < 64:
+        raise ValueError("seed must be a contiguous float32 or float64 GPU tensor of 64 values")
+    need = 2 * launch.grid_blocks * launch.block_threads
     if sink is None:
-        sink = torch.empty(2 * launch.grid_blocks * launch.block_threads, dtype=torch.float64,
-                           device=seed.device)
+        sink = torch.empty(need, dtype=torch.float64, device=seed.device)
+    elif sink.device != seed.device or sink.element_size() != 8 or not sink.is_contiguous() or \
+            sink.numel() < need:
+        raise ValueError("sink must be a contiguous 8-byte tensor of 2 * grid_blocks * "
+                         "block_threads entries")
     check("twofold_probe_compute", L.twofold_probe_compute(
         seed.element_size(), int(is_dot), mode_id(mode), ctypes.c_void_p(seed.data_ptr()), iters,
         ctypes.byref(launch), ctypes.c_void_p(sink.data_ptr()), _stream_ptr(seed.device)))

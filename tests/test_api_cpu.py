@@ -276,3 +276,18 @@ def test_mixed_mode_argument_checks():
     assert L.twofold_dot_mixed_f32(fake, fake, 10, None, ctypes.c_void_p(0x10004), ws, big,
                                    None) == EALIGN  # binary64 output pair
     assert L.twofold_sum_mixed_f32(fake, 1 << 24, None, fake, ws, 256, None) == EWORKSPACE
+
+
+def test_binding_checks_caller_outputs():
+    """A caller's out tensor must hold the library's rows in the result type:
+    a binary32 tensor given for binary64 rows, or too few elements, is
+    refused before anything reaches the library (it would be overrun)."""
+    import torch
+    import paper_1401_0248_amd as tf
+    ok = torch.empty((3, 2), dtype=torch.float64)
+    assert tf._out(ok, 3, torch.float64, "cpu", (3, 2)) is ok
+    assert tf._out(None, 3, torch.float64, "cpu", (3, 2)).shape == (3, 2)
+    for bad in (torch.empty((3, 2), dtype=torch.float32), torch.empty((2, 2), dtype=torch.float64),
+                torch.empty((3, 4), dtype=torch.float64)[:, :2]):
+        with pytest.raises(ValueError):
+            tf._out(bad, 3, torch.float64, "cpu", (3, 2))

@@ -172,6 +172,10 @@ def test_multi_rejects_bad_input():
         tf.multisum([x], "mixed")  # binary64 rows: multisum_mixed
     with pytest.raises(TypeError):
         tf.multisum_mixed([x.double()])
+    with pytest.raises(ValueError):  # binary64 rows do not fit a binary32 out
+        tf.multisumd([x, x], out=torch.empty((2, 2), dtype=torch.float32, device="cuda:0"))
+    with pytest.raises(ValueError):
+        tf.multisum([x, x], out=torch.empty((1, 2), dtype=torch.float32, device="cuda:0"))
     with pytest.raises(tf.TwofoldError):
         tf.multidot([x[1:]], [x[:-1]], "rigorous", launch(100, 4, 1))
 
