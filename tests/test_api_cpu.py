@@ -291,3 +291,22 @@ def test_binding_checks_caller_outputs():
                 torch.empty((3, 4), dtype=torch.float64)[:, :2]):
         with pytest.raises(ValueError):
             tf._out(bad, 3, torch.float64, "cpu", (3, 2))
+
+
+def test_bench_input_placement():
+    """bench.py's input buffer: every array keeps its values, starts 256
+    bytes aligned relative to the buffer, and is followed by the gap."""
+    import torch
+    import bench
+    host = {("a", 1): (np.arange(10, dtype=np.float32), np.ones(10, dtype=np.float32)),
+            ("b", 2): (np.arange(7, dtype=np.float64), -np.ones(7))}
+    d = bench.place_inputs(torch, host, "cpu")
+    base = d[("a", 1)][0].data_ptr()
+    prev_end = None
+    for k, (x, y) in host.items():
+        for a, t in zip((x, y), d[k]):
+            assert np.array_equal(t.numpy(), a)
+            assert (t.data_ptr() - base) % 256 == 0
+            if prev_end is not None:
+                assert t.data_ptr() - prev_end >= bench.INPUT_GAP
+            prev_end = t.data_ptr() + a.nbytes

@@ -178,6 +178,43 @@ def test_plan_graph_replay():
         assert torch.equal(plan.execute(xd, yd), eager)
 
 
+def test_device_offset_calls_graph_replay():
+    """Device-offset calls (tile table built on the device, then the tile and
+    combine kernels) captured into a HIP graph: every replay, with other
+    work between replays, equals the eager result bit for bit. Binary32 data
+    in the mixed form and in sumd (binary64 rows), and a rigorous binary32
+    dot (binary32 rows)."""
+    L = synth.segment_lengths(9, 400, max_len=1 << 14)
+    off = synth.offsets_from_lengths(L)
+    x, y = synth.uniform(10, int(off[-1]), np.float32, count=2)
+    xd, _ = to_dev(x, 1)
+    yd, _ = to_dev(y, 1)
+    od = torch.from_numpy(off).to(DEV)
+    calls = [lambda o, w: tf.segdot_mixed(xd, yd, od, out=o, ws=w),
+             lambda o, w: tf.segsumd(xd, od, out=o, ws=w),
+             lambda o, w: tf.segdot(xd, yd, od, "rigorous", out=o, ws=w)]
+    eager = [tf.segdot_mixed(xd, yd, od), tf.segsumd(xd, od), tf.segdot(xd, yd, od, "rigorous")]
+    outs = [torch.empty_like(e) for e in eager]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        wss = [tf.Workspace(1 << 22, xd.device) for _ in calls]
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for c, o, w in zip(calls, outs, wss):
+            c(o, w)
+    for i in range(4):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for e, o in zip(eager, outs):
+            assert torch.equal(o.view(torch.int8), e.view(torch.int8)), i
+        tf.segdot_mixed(yd, xd, od)  # other work on the same tensors between replays
+        torch.cuda.synchronize()
+
+
 def test_plan_after_device_path_on_shared_workspace():
     """A device-offset call with few segments, then one with many, then a
     plan with many more, all on the same per-stream workspace: the plan's
