@@ -281,6 +281,35 @@ int twofold_multidot_mixed_f32(const float* const* x, const float* const* y, con
                                int64_t count, const twofold_launch_t* launch, twofold_f64_t* out,
                                void* ws, size_t ws_bytes, void* stream);
 
+/* ---- a mixed batch: up to 64 sums and dots of either data type and any
+ * form in one launch ---------------------------------------------------------
+ * Each item names its data (device pointers), its length, its data type (4
+ * or 8), whether it is a dot, its mode (the modes whose results have the
+ * data's type: TWOFOLD_WIDE and TWOFOLD_MIXED give EINVAL) and its output
+ * pair (device twofold_f32_t or twofold_f64_t, by the data type). items is a
+ * HOST array. Every item's pair is bitwise the one its single-vector call
+ * (twofold_sum_* / twofold_dot_*) returns with the batch's launch; launch
+ * NULL takes the default launch of the item that reads the most bytes. As in
+ * the multi-vector calls, items of at most 64 MiB each run side by side,
+ * longer ones in turn through one block set, and one combine kernel
+ * finishes them all, so a batch pays the per-launch costs once.
+ * Workspace: twofold_workspace_bytes_batch (count times the single-vector
+ * workspace of the launch); count = 0 does nothing. */
+typedef struct {
+  const void* x;   /* device data, n elements of dtype bytes */
+  const void* y;   /* device data for a dot; ignored for a sum */
+  void* out;       /* device output pair of the data's type */
+  int64_t n;
+  int32_t dtype;   /* 4: binary32, 8: binary64 */
+  int32_t is_dot;  /* 0: sum of x, 1: dot of x and y */
+  int32_t mode;    /* TWOFOLD_PLAIN ... TWOFOLD_RIGOROUS_ROUNDED, not WIDE or MIXED */
+  int32_t reserved;
+} twofold_batch_item_t;
+size_t twofold_workspace_bytes_batch(const twofold_batch_item_t* items, int64_t count,
+                                     const twofold_launch_t* launch);
+int twofold_batch(const twofold_batch_item_t* items, int64_t count,
+                  const twofold_launch_t* launch, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- segmented (CSR) batches: nseg pairs into out[0..nseg) ---------------
  * offsets: device int64[nseg + 1], non-decreasing, offsets[0] >= 0 and
  * offsets[nseg] <= n_total (the length of x and y). Checked on the device:

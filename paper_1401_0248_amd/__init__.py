@@ -254,6 +254,49 @@ def multidot_mixed(xs, ys, launch=None, out=None, ws=None):
     return _multi("twofold_multidot_mixed_f32", xs, ys, MIXED, launch, out, ws)
 
 
+MAX_BATCH = 64  # items per batch call
+
+
+def batch(items, launch=None, outs=None, ws=None):
+    """Up to 64 sums and dots of either data type and any mode with results
+    of the data's type, in one launch (twofold_batch). items: (x, y, mode)
+    tuples, y None for a sum. Returns one tensor([value, error]) per item,
+    bitwise the sum()/dot() of that item with the batch's launch (default:
+    the launch of the item that reads the most bytes)."""
+    L = _lib.load()
+    items = list(items)
+    count = len(items)
+    if not 1 <= count <= MAX_BATCH:
+        raise ValueError("twofold: a batch takes 1..%d items" % MAX_BATCH)
+    if outs is not None and len(outs) != count:
+        raise ValueError("twofold: one out per item")
+    dev = items[0][0].device
+    arr = (_lib.BatchItem * count)()
+    res = []
+    for v, (x, y, mode) in enumerate(items):
+        _check_data(*([x] if y is None else [x, y]))
+        if x.device != dev:
+            raise ValueError("twofold: all items must be on one device")
+        o = _out(None if outs is None else outs[v], 1, x.dtype, dev, (2,))
+        res.append(o)
+        arr[v].x = x.data_ptr()
+        arr[v].y = y.data_ptr() if y is not None else None
+        arr[v].out = o.data_ptr()
+        arr[v].n = x.numel()
+        arr[v].dtype = x.element_size()
+        arr[v].is_dot = int(y is not None)
+        arr[v].mode = mode_id(mode)
+    lp = _launch_ptr(launch)
+    need = L.twofold_workspace_bytes_batch(ctypes.cast(arr, ctypes.c_void_p), count, lp)
+    if need == 0:
+        raise TwofoldError("twofold_workspace_bytes_batch", _lib.EINVAL)
+    if ws is None:
+        ws = workspace(need, dev)
+    check("twofold_batch", L.twofold_batch(ctypes.cast(arr, ctypes.c_void_p), count, lp,
+                                           ctypes.c_void_p(ws.ptr), ws.nbytes, _stream_ptr(dev)))
+    return res
+
+
 def sum_mixed(x, launch=None, out=None, ws=None):
     """Rigorous twofold sum of float32 data with a float64 error term: a
     float64 tensor([value, error]) whose value is sum(x, "rigorous")'s."""

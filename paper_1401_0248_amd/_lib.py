@@ -75,8 +75,17 @@ SIGNATURES = {
     "twofold_monitor": (_int, [_int, _vp, _i64, _vp, _i64, ctypes.c_double, _vp, _vp, _vp]),
     "twofold_probe_read": (_int, [_vp, _vp, _i64, _LP, _vp, _vp]),
     "twofold_probe_compute": (_int, [_int, _int, _int, _vp, _i64, _LP, _vp, _vp]),
+    "twofold_workspace_bytes_batch": (_sz, [_vp, _i64, _LP]),
+    "twofold_batch": (_int, [_vp, _i64, _LP, _vp, _sz, _vp]),
     "twofold_strerror": (ctypes.c_char_p, [_int]),
 }
+
+class BatchItem(ctypes.Structure):
+    """twofold_batch_item_t of include/twofold.h."""
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("dtype", ctypes.c_int32), ("is_dot", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
 
 _lib = None
 

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtwofold.so")
-SOURCES = ["twofold.hip", "segmented.hip", "monitor.hip", "probes.hip"]
+SOURCES = ["twofold.hip", "segmented.hip", "monitor.hip", "probes.hip", "batch.hip"]
 DEPS = SOURCES + ["eft.hpp", "kernels.hpp", "host_common.hpp", "tuned_table.inc"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

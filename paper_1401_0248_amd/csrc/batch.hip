@@ -1,0 +1,211 @@
+// batch.hip: a mixed batch of sums and dots in one launch (twofold_batch in
+// include/twofold.h). Items may differ in data type, operation and form;
+// each is reduced exactly as its single-vector call with the batch's launch
+// (steps 1-8), so its pair is that call's, bit for bit. The per-item form is
+// a uniform branch at the item's start: every block takes the same path.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "host_common.hpp"
+#include "kernels.hpp"
+#include "twofold.h"
+
+namespace twofold {
+
+constexpr int kMaxBatch = 64;
+
+// One item as the kernels see it. kind = f64 | dot << 1 | yv << 2 | mode << 3.
+struct BatchEntry {
+  const void* x;
+  const void* y;
+  void* out;
+  int64_t n;
+  int64_t kind;
+};
+
+struct BatchArgs {
+  BatchEntry e[kMaxBatch];
+};
+
+template <typename T, bool DOT, bool YV, int U>
+__device__ __forceinline__ void batch_item(const BatchEntry& b, int mode, double* part) {
+  const T* x = static_cast<const T*>(b.x);
+  const T* y = static_cast<const T*>(b.y);
+  switch (mode) {
+    case kPlain: single_block<T, T, kPlain, DOT, YV, U>(x, y, b.n, part, b.out, 0); break;
+    case kFast: single_block<T, T, kFast, DOT, YV, U>(x, y, b.n, part, b.out, 0); break;
+    case kRigorous: single_block<T, T, kRigorous, DOT, YV, U>(x, y, b.n, part, b.out, 0); break;
+    case kKahan: single_block<T, T, kKahan, DOT, YV, U>(x, y, b.n, part, b.out, 0); break;
+    case kFastRounded:
+      if constexpr (DOT) single_block<T, T, kFastRounded, DOT, YV, U>(x, y, b.n, part, b.out, 0);
+      break;
+    default:
+      if constexpr (DOT) single_block<T, T, kRigorousRounded, DOT, YV, U>(x, y, b.n, part, b.out, 0);
+      break;
+  }
+}
+
+template <typename T, int U>
+__device__ __forceinline__ void batch_by_op(const BatchEntry& b, int64_t kind, double* part) {
+  const int mode = static_cast<int>(kind >> 3);
+  if (kind & 2) {
+    if (kind & 4)
+      batch_item<T, true, true, U>(b, mode, part);
+    else
+      batch_item<T, true, false, U>(b, mode, part);
+  } else {
+    batch_item<T, false, true, U>(b, mode, part);
+  }
+}
+
+// Pass 1: sets of gridDim.x blocks as in the multi-vector kernel; item v's
+// block pairs at part[v * gridDim.x ...].
+template <int U>
+__global__ void __launch_bounds__(1024)
+batch_kernel(const BatchArgs args, int count, double* __restrict__ part) {
+  for (int v = blockIdx.y; v < count; v += gridDim.y) {
+    const BatchEntry& b = args.e[v];
+    double* p = part + 2 * static_cast<int64_t>(v) * gridDim.x;
+    if (b.kind & 1)
+      batch_by_op<double, U>(b, b.kind, p);
+    else
+      batch_by_op<float, U>(b, b.kind, p);
+    __syncthreads();  // the block combine's LDS is reused for the next item
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void batch_pass2_by_mode(const BatchEntry& b, const double2* pairs,
+                                                    int nparts) {
+  switch (static_cast<int>(b.kind >> 3)) {
+    case kPlain: pass2_block<T, kPlain>(pairs, nparts, b.out, 0); break;
+    case kFast: pass2_block<T, kFast>(pairs, nparts, b.out, 0); break;
+    case kRigorous: pass2_block<T, kRigorous>(pairs, nparts, b.out, 0); break;
+    case kKahan: pass2_block<T, kKahan>(pairs, nparts, b.out, 0); break;
+    case kFastRounded: pass2_block<T, kFastRounded>(pairs, nparts, b.out, 0); break;
+    default: pass2_block<T, kRigorousRounded>(pairs, nparts, b.out, 0); break;
+  }
+}
+
+// Pass 2: block v combines item v's block pairs (step 7) and finalizes.
+__global__ void __launch_bounds__(kPass2Lanes)
+batch_pass2_kernel(const BatchArgs args, const double* __restrict__ part, int nparts) {
+  const BatchEntry& b = args.e[blockIdx.x];
+  const double2* pairs =
+      reinterpret_cast<const double2*>(part) + static_cast<int64_t>(blockIdx.x) * nparts;
+  if (b.kind & 1)
+    batch_pass2_by_mode<double>(b, pairs, nparts);
+  else
+    batch_pass2_by_mode<float>(b, pairs, nparts);
+}
+
+}  // namespace twofold
+
+using namespace twofold;
+using namespace twofold::host;
+
+namespace {
+
+// Items that read at most this much each run side by side (one block set
+// each), as in the multi-vector calls; otherwise one set walks them in turn.
+constexpr int64_t kBatchSideBytes = int64_t(1) << 26;
+
+bool batch_mode_ok(int dtype, bool dot, int mode) {
+  return mode_ok(dtype, dot, mode) && mode != kWide && mode != kMixed;
+}
+
+int64_t item_bytes(const twofold_batch_item_t& it) {
+  return it.n * it.dtype * (it.is_dot ? 2 : 1);
+}
+
+// Checks every item; the launch is the single-vector one of the item that
+// reads the most bytes (the first such), or the given one.
+int resolve_batch(const twofold_batch_item_t* items, int64_t count,
+                  const twofold_launch_t* launch, twofold_launch_t* lc, int64_t* max_bytes) {
+  if (count < 0 || count > kMaxBatch || (count > 0 && !items)) return TWOFOLD_EINVAL;
+  int64_t best = -1, bi = 0;
+  for (int64_t v = 0; v < count; v++) {
+    const twofold_batch_item_t& it = items[v];
+    if (!valid_dtype(it.dtype) || !valid_count(it.n) || (it.is_dot != 0 && it.is_dot != 1) ||
+        !batch_mode_ok(it.dtype, it.is_dot != 0, it.mode))
+      return TWOFOLD_EINVAL;
+    if (item_bytes(it) > best) {
+      best = item_bytes(it);
+      bi = v;
+    }
+  }
+  *max_bytes = best < 0 ? 0 : best;
+  if (count == 0) return TWOFOLD_OK;
+  const twofold_batch_item_t& m = items[bi];
+  return resolve_single(m.dtype, m.is_dot != 0, m.mode, m.n, launch, lc);
+}
+
+template <int U>
+int launch_batch_u(const BatchArgs& a, int count, int sets, const twofold_launch_t& lc,
+                   double* part, hipStream_t st) {
+  batch_kernel<U><<<dim3(lc.grid_blocks, unsigned(sets)), dim3(lc.block_threads), 0, st>>>(
+      a, count, part);
+  if (launch_status()) return TWOFOLD_EHIP;
+  if (lc.grid_blocks > 1) {
+    batch_pass2_kernel<<<dim3(unsigned(count)), dim3(kPass2Lanes), 0, st>>>(a, part,
+                                                                            lc.grid_blocks);
+    return launch_status();
+  }
+  return TWOFOLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t twofold_workspace_bytes_batch(const twofold_batch_item_t* items, int64_t count,
+                                     const twofold_launch_t* launch) {
+  twofold_launch_t lc;
+  int64_t mb = 0;
+  if (resolve_batch(items, count, launch, &lc, &mb)) return 0;
+  if (count == 0) return align256(16);
+  return multi_ws_bytes(lc, count);
+}
+
+int twofold_batch(const twofold_batch_item_t* items, int64_t count,
+                  const twofold_launch_t* launch, void* ws, size_t ws_bytes, void* stream) {
+  twofold_launch_t lc;
+  int64_t max_bytes = 0;
+  const int rc = resolve_batch(items, count, launch, &lc, &max_bytes);
+  if (rc) return rc;
+  BatchArgs a;
+  for (int64_t v = 0; v < count; v++) {
+    const twofold_batch_item_t& it = items[v];
+    const bool dot = it.is_dot != 0;
+    // data pointers may be NULL only when there is no data
+    if (!it.out || (!it.x && it.n > 0) || (dot && !it.y && it.n > 0)) return TWOFOLD_EINVAL;
+    if (!elem_aligned(it.x, it.dtype) || (dot && !elem_aligned(it.y, it.dtype)) ||
+        !elem_aligned(it.out, it.dtype))
+      return TWOFOLD_EALIGN;
+    const bool yv = !dot || ((reinterpret_cast<uintptr_t>(it.y) -
+                              reinterpret_cast<uintptr_t>(it.x)) & 15u) == 0;
+    a.e[v].x = it.x;
+    a.e[v].y = dot ? it.y : nullptr;
+    a.e[v].out = it.out;
+    a.e[v].n = it.n;
+    a.e[v].kind = int64_t(it.dtype == 8) | (int64_t(dot) << 1) | (int64_t(yv) << 2) |
+                  (int64_t(it.mode) << 3);
+  }
+  for (int64_t v = count; v < kMaxBatch; v++) a.e[v] = BatchEntry{nullptr, nullptr, nullptr, 0, 0};
+  if (count == 0) return TWOFOLD_OK;
+  if (lc.grid_blocks > 1 && !ws_ok(ws, ws_bytes, multi_ws_bytes(lc, count)))
+    return TWOFOLD_EWORKSPACE;
+  const int sets = max_bytes <= kBatchSideBytes ? int(count) : 1;
+  double* part = static_cast<double*>(ws);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int c = int(count);
+  switch (lc.unroll) {
+    case 1: return launch_batch_u<1>(a, c, sets, lc, part, st);
+    case 2: return launch_batch_u<2>(a, c, sets, lc, part, st);
+    case 4: return launch_batch_u<4>(a, c, sets, lc, part, st);
+    default: return launch_batch_u<8>(a, c, sets, lc, part, st);
+  }
+}
+
+}  // extern "C"

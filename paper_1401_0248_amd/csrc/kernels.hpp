@@ -357,13 +357,12 @@ __device__ __forceinline__ void combine_strided(const double2* __restrict__ p, i
 // pairs of vector b (part[b * nparts ...]; one block for a single-vector
 // call) in binary64, lane l taking pairs l, l + 256, ... in order.
 template <typename T, int M>
-__global__ void __launch_bounds__(kPass2Lanes)
-single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restrict__ out) {
+__device__ __forceinline__ void pass2_block(const double2* __restrict__ pairs, int nparts,
+                                            void* __restrict__ out, int64_t idx) {
   __shared__ double sh_s[kPass2Lanes / 64], sh_e[kPass2Lanes / 64];
   constexpr int P = pass2_mode(M);
   double qs = 0.0, qe = 0.0;
-  combine_strided<P>(reinterpret_cast<const double2*>(part) + static_cast<int64_t>(blockIdx.x) * nparts,
-                     nparts, threadIdx.x, kPass2Lanes, qs, qe);
+  combine_strided<P>(pairs, nparts, threadIdx.x, kPass2Lanes, qs, qe);
   wave_combine<P>(qs, qe);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) {
@@ -374,8 +373,15 @@ single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restric
   if (threadIdx.x == 0) {
     double V = sh_s[0], E = sh_e[0];
     for (int w = 1; w < kPass2Lanes / 64; w++) combine<P>(V, E, sh_s[w], sh_e[w]);
-    finalize_store<T, M>(out, blockIdx.x, V, E);
+    finalize_store<T, M>(out, idx, V, E);
   }
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(kPass2Lanes)
+single_pass2_kernel(const double* __restrict__ part, int nparts, void* __restrict__ out) {
+  pass2_block<T, M>(reinterpret_cast<const double2*>(part) + static_cast<int64_t>(blockIdx.x) * nparts,
+                    nparts, out, blockIdx.x);
 }
 
 // ---- segmented ---------------------------------------------------------------

@@ -310,3 +310,44 @@ def test_bench_input_placement():
             if prev_end is not None:
                 assert t.data_ptr() - prev_end >= bench.INPUT_GAP
             prev_end = t.data_ptr() + a.nbytes
+
+
+def test_batch_argument_checks():
+    """twofold_batch checks every item on the host before any HIP call."""
+    from paper_1401_0248_amd._lib import BatchItem
+    L = _lib.load()
+    ws = ctypes.c_void_p(0x100000)
+
+    def items(*specs):
+        arr = (BatchItem * len(specs))()
+        for v, (x, y, out, n, dt, dot, mode) in enumerate(specs):
+            arr[v].x, arr[v].y, arr[v].out, arr[v].n = x, y, out, n
+            arr[v].dtype, arr[v].is_dot, arr[v].mode = dt, dot, mode
+        return arr
+
+    ok = (0x10000, 0x20000, 0x30000, 100, 8, 1, 2)
+    big = 1 << 20
+    assert L.twofold_batch(items(ok), 65, None, ws, big, None) == EINVAL
+    assert L.twofold_batch(items(ok), -1, None, ws, big, None) == EINVAL
+    assert L.twofold_batch(None, 2, None, ws, big, None) == EINVAL
+    assert L.twofold_batch(None, 0, None, ws, big, None) == 0  # nothing to do
+    for bad in ((0x10000, 0x20000, 0x30000, 100, 8, 1, 3),   # wide: binary64 rows elsewhere
+                (0x10000, 0x20000, 0x30000, 100, 4, 1, 7),   # mixed
+                (0x10000, 0, 0x30000, 100, 8, 0, 5),         # rounded-product sum
+                (0x10000, 0x20000, 0x30000, 100, 2, 1, 2),   # dtype
+                (0x10000, 0x20000, 0x30000, -1, 8, 1, 2),    # length
+                (0x10000, 0x20000, 0x30000, 100, 8, 2, 2),   # is_dot
+                (0x10000, 0x20000, None, 100, 8, 1, 2),      # out
+                (None, 0x20000, 0x30000, 100, 8, 1, 2),      # x
+                (0x10000, None, 0x30000, 100, 8, 1, 2)):     # y of a dot
+        assert L.twofold_batch(items(ok, bad), 2, None, ws, big, None) == EINVAL, bad
+    for mis in ((0x10004, 0x20000, 0x30000, 100, 8, 1, 2), (0x10000, 0x20000, 0x30004, 100, 8, 1, 2)):
+        assert L.twofold_batch(items(ok, mis), 2, None, ws, big, None) == EALIGN, mis
+    # workspace: count times the single-vector one of the largest item's launch
+    two = items((0x10000, 0x20000, 0x30000, 1 << 24, 8, 1, 2), (0x10000, 0, 0x30000, 5, 4, 0, 1))
+    need = L.twofold_workspace_bytes_batch(two, 2, None)
+    one = L.twofold_workspace_bytes_single(8, 1, 2, 1 << 24, None)
+    assert need >= 2 * (one - 255)
+    assert L.twofold_batch(two, 2, None, ws, need - 256, None) == EWORKSPACE
+    assert L.twofold_workspace_bytes_batch(items((0x10000, 0x20000, 0x30000, 100, 8, 1, 3)), 1,
+                                           None) == 0
