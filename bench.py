@@ -2,22 +2,21 @@
 
 Workload (one step): the fast and the rigorous twofold dot of 12 resident
 vector pairs of N = 2^24 elements, binary32 and binary64, generated with
-target conditions 1e6, 1e8, ..., 1e16 (synth.illcond_dot). The step makes
-four multi-vector calls, one per (type, form), each reducing its type's six
-pairs in one launch; the rigorous calls run first, so no pair is re-read
-while it could still sit in the 256 MB last-level cache. Prints one JSON
-line.
+target conditions 1e6, 1e8, ..., 1e16 (synth.illcond_dot). The step is one
+mixed batch call: the 24 dots in one launch and one combine kernel; the
+rigorous dots run first, so no pair is re-read while it could still sit in
+the 256 MB last-level cache. Prints one JSON line.
 
-The dominant kernel is the binary64 rigorous call (six pairs, 1.5 GiB per
-launch); its average duration is measured with HIP events on the launch
-stream during the timed steps and gives the roofline entry (algorithmic
-bytes / time vs 8 TB/s). The same six dots as single-vector calls are timed
-after the timed region for reference. The CPU-baseline leg, the only part that runs the oracle, times
+The dominant kernel is the batch (4.5 GiB per launch); its average duration
+is measured with HIP events on the launch stream during the timed steps and
+gives the roofline entry (algorithmic bytes / time vs 8 TB/s). Every dot is
+checked bit for bit against its single-vector call with the same launch
+after the timed region, and the binary64 rigorous single calls are timed for
+reference. The CPU-baseline leg, the only part that runs the oracle, times
 the oracle's sequential paper-order loops on one host thread over the same
 inputs and grades every form's GPU result against the exact sum.
 """
 import argparse
-import ctypes
 import json
 import os
 import sys
@@ -535,8 +534,8 @@ def calibrate_copy(torch, dev):
                       "bytes_written": COPY_BYTES, "dispatches": 5}), flush=True)
 
 
-KERNEL_SOURCES = ("eft.hpp", "kernels.hpp", "host_common.hpp", "twofold.hip", "tuned_table.inc")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_f64_rigorous_dot_n2e24.json")
+KERNEL_SOURCES = ("eft.hpp", "kernels.hpp", "host_common.hpp", "batch.hip", "tuned_table.inc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_illcond_batch_n2e24.json")
 
 
 def kernel_sources_sha256():
@@ -610,38 +609,28 @@ def main():
     f64 = sorted((k for k in dev_in if k[0] == np.float64), key=lambda k: k[1])
     f32 = sorted((k for k in dev_in if k[0] == np.float32), key=lambda k: k[1])
     keys = {np.float64: f64, np.float32: f32}
-    forms = [(np.float64, "rigorous"), (np.float32, "rigorous"), (np.float64, "fast"),
-             (np.float32, "fast")]
-    outs = {(dt, m): torch.empty((len(keys[dt]), 2), dtype=dev_in[keys[dt][0]][0].dtype,
-                                 device=dev) for dt, m in forms}
-    L = tf._lib.load()
-    ns = (ctypes.c_int64 * 6)(*([N] * 6))
-    ws_bytes = max(L.twofold_workspace_bytes_multi(8, 1, 2, ns, 6, None),
-                   L.twofold_workspace_bytes_multi(4, 1, 2, ns, 6, None))
-    ws = tf.Workspace(ws_bytes, dev)
-
-    # One step: four multi-vector calls, one per (type, form), each reducing
-    # the six pairs of its type in one launch. A = the binary64 rigorous call
-    # (the dominant kernel, bracketed by events); B = binary32 rigorous,
-    # binary64 fast, binary32 fast, in that order, so that between two reads
-    # of one pair at least 768 MiB of other pairs is read and no pair is
-    # served from the 256 MB last-level cache.
-    def multi(dt, mode):
-        ks = keys[dt]
-        tf.multidot([dev_in[k][0] for k in ks], [dev_in[k][1] for k in ks], mode,
-                    out=outs[(dt, mode)], ws=ws)
+    # One step: the rigorous and the fast dot of every pair, 24 items of both
+    # data types in one mixed batch (one launch, one combine kernel). The
+    # items run in turn in the order binary64 rigorous, binary32 rigorous,
+    # binary64 fast, binary32 fast, so that between two reads of one pair at
+    # least 768 MiB of other pairs is read and no pair is served from the
+    # 256 MB last-level cache.
+    items = [(k, m) for m, ks in (("rigorous", f64), ("rigorous", f32), ("fast", f64),
+                                  ("fast", f32)) for k in ks]
+    calls = [(dev_in[k][0], dev_in[k][1], m) for k, m in items]
+    outs = [torch.empty(2, dtype=dev_in[k][0].dtype, device=dev) for k, _ in items]
+    # the batch's launch: the default of its largest item, a binary64 rigorous dot
+    lc = tf.default_launch(0, 8, True, "rigorous", N)
+    ws = tf.Workspace(1 << 20, dev)
+    bytes_step = sum(2 * N * dev_in[k][0].element_size() for k, _ in items)
 
     cap = torch.cuda.Stream(dev)
-    for dt, m in forms:  # eager run first: loads the library, checks the calls
-        multi(dt, m)
+    tf.batch(calls, outs=outs, ws=ws)  # eager run first: loads the library, checks the call
     torch.cuda.synchronize()
-    eager = {k: v.clone() for k, v in outs.items()}
-    gA, gB = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
-    with torch.cuda.graph(gA, stream=cap):
-        multi(*forms[0])
-    with torch.cuda.graph(gB, stream=cap):
-        for f in forms[1:]:
-            multi(*f)
+    eager = [o.clone() for o in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cap):
+        tf.batch(calls, outs=outs, ws=ws)
     stream = torch.cuda.current_stream(dev)
     ev = []
 
@@ -650,12 +639,11 @@ def main():
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            gA.replay()
+            g.replay()
             e1.record(stream)
             ev.append((e0, e1))
         else:
-            gA.replay()
-        gB.replay()
+            g.replay()
 
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
@@ -668,35 +656,37 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = 1e3 * elapsed / args.steps
-    ndots = 2 * len(dev_in)
+    ndots = len(items)
     value = ndots * N * args.steps / elapsed / 1e9
     launches_s = [a.elapsed_time(b) * 1e-3 for a, b in ev]
     avg = sum(launches_s) / len(launches_s)
-    bytes_launch = len(f64) * 2 * N * 8  # six pairs of binary64 x and y
-    achieved = bytes_launch / avg / 1e9
-    lc = tf.default_launch(0, 8, True, "rigorous", N)
+    achieved = bytes_step / avg / 1e9
     # every result of the last timed step against the eager run, bit for bit
-    repeatable = all(torch.equal(eager[k].view(torch.int8), outs[k].view(torch.int8))
-                     for k in outs)
-    log("step %.3f ms, %.1f Gelem/s; f64 rigorous multi-vector call %.1f us avg, %.0f GB/s"
+    repeatable = all(torch.equal(e.view(torch.int8), o.view(torch.int8))
+                     for e, o in zip(eager, outs))
+    log("step %.3f ms, %.1f Gelem/s; batch launch %.1f us avg by events, %.0f GB/s"
         % (ms_step, value, avg * 1e6, achieved))
 
-    # After the timed region, for reference: the same six dots as six
-    # single-vector calls (graph replay), whose results the multi-vector call
-    # must match bit for bit.
-    single = torch.empty((len(f64), 2), dtype=torch.float64, device=dev)
-    ws1 = tf.Workspace(L.twofold_workspace_bytes_single(8, 1, 2, N, None), dev)
+    # After the timed region, for reference: every item as a single-vector
+    # call with the batch's launch (results must match the batch bit for
+    # bit), and the time of the six binary64 rigorous dots as single calls.
+    single = [torch.empty(2, dtype=dev_in[k][0].dtype, device=dev) for k, _ in items]
+    ws1 = tf.Workspace(1 << 20, dev)
+    for i, (x, y, m) in enumerate(calls):
+        tf.dot(x, y, m, lc, out=single[i], ws=ws1)
+    batch_same = all(torch.equal(a.view(torch.int8), b.view(torch.int8))
+                     for a, b in zip(single, outs))
+    f64r = [i for i, (k, m) in enumerate(items) if k[0] == np.float64 and m == "rigorous"]
 
     def singles():
-        for i, k in enumerate(f64):
-            tf.dot(dev_in[k][0], dev_in[k][1], "rigorous", out=single[i], ws=ws1)
-        return len(f64)
+        for i in f64r:
+            tf.dot(calls[i][0], calls[i][1], "rigorous", lc, out=single[i], ws=ws1)
+        return len(f64r)
 
     single_med, _ = graph_time(torch, singles, reps=20)
-    multi_same = torch.equal(single.view(torch.int8), outs[forms[0]].view(torch.int8))
     single_gbs = 2 * N * 8 / single_med / 1e9
-    log("single-vector calls: %.1f us per call, %.0f GB/s; multi == single: %s"
-        % (single_med * 1e6, single_gbs, multi_same))
+    log("single-vector calls: %.1f us per call, %.0f GB/s; batch == single calls: %s"
+        % (single_med * 1e6, single_gbs, batch_same))
 
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "Gelem/s", "n_gpus": 1,
@@ -704,23 +694,25 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "ill-conditioned twofold dot, fast+rigorous, f32 and f64, "
-                               "N=2^24, target cond 1e6..1e16 (12 pairs, 24 dots per step as "
-                               "four multi-vector calls of six pairs, HIP-graph replay)",
+                               "N=2^24, target cond 1e6..1e16 (12 pairs, 24 dots per step in "
+                               "one mixed batch launch, HIP-graph replay)",
                    "n": N, "pairs": len(dev_in), "dots_per_step": ndots},
         "bitwise_repeatable": repeatable,
-        "multi_equals_single_calls": multi_same,
+        "batch_equals_single_calls": batch_same,
         "device": device_info(torch, dev),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
-                     "kernel": "binary64 rigorous twofold dot of six N=2^24 pairs in one "
-                               "multi-vector call (multi_kernel + single_pass2_kernel)",
-                     "launch": lc.as_dict(), "bytes_per_launch": bytes_launch,
+                     "kernel": "the step's mixed batch: 24 twofold dots of N=2^24 (binary64 and "
+                               "binary32, rigorous and fast) in one launch (batch_kernel + "
+                               "batch_pass2_kernel)",
+                     "launch": lc.as_dict(), "bytes_per_launch": bytes_step,
                      "avg_launch_us": round(avg * 1e6, 2),
                      "single_call": {"avg_us": round(single_med * 1e6, 2),
                                      "achieved": round(single_gbs, 1),
                                      "frac": round(single_gbs / HBM_PEAK_GBS, 4),
-                                     "note": "the same dots as six single-vector calls "
+                                     "note": "a binary64 rigorous dot of the step as a "
+                                             "single-vector call with the same launch "
                                              "(single_kernel + single_pass2_kernel), graph "
                                              "replay median per call, after the timed region"}},
     }
