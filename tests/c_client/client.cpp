@@ -110,6 +110,18 @@ int main(void) {
   const int rcx = twofold_dot_mixed_f32(xf, xf, kN, NULL, &outw[0], xws, xwsb, st);
   // the same workspace: calls on one stream run in order
   const int rcw = twofold_multisumd_f64(wx, wn, 2, NULL, &outw[1], xws, xwsb, st);
+
+  // a mixed batch: the binary64 dot and the binary32 fast sum in one launch
+  twofold_f64_t* outb64;
+  twofold_f32_t* outb32;
+  HIP_OK(hipMalloc((void**)&outb64, sizeof(twofold_f64_t)));
+  HIP_OK(hipMalloc((void**)&outb32, sizeof(twofold_f32_t)));
+  twofold_batch_item_t bi[2] = {{x, y, outb64, kN, 8, 1, TWOFOLD_RIGOROUS, 0},
+                                {xf, NULL, outb32, kN, 4, 0, TWOFOLD_FAST, 0}};
+  size_t bwsb = twofold_workspace_bytes_batch(bi, 2, NULL);
+  void* bws;
+  HIP_OK(hipMalloc(&bws, bwsb));
+  const int rcb = twofold_batch(bi, 2, NULL, bws, bwsb, st);
   HIP_OK(hipStreamSynchronize(st));
 
   twofold_f64_t r64[8];
@@ -138,6 +150,12 @@ int main(void) {
   printf("dot_mixed_f32 %d %a %a\n", rcx, rw[0].value, rw[0].error);
   for (int v = 0; v < 2; v++)
     printf("multisumd_f64_%d %d %a %a\n", v, rcw, rw[1 + v].value, rw[1 + v].error);
+  twofold_f64_t rb64;
+  twofold_f32_t rb32;
+  HIP_OK(hipMemcpy(&rb64, outb64, sizeof(rb64), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(&rb32, outb32, sizeof(rb32), hipMemcpyDeviceToHost));
+  printf("batch_dot_f64_rigorous %d %a %a\n", rcb, rb64.value, rb64.error);
+  printf("batch_sum_f32_fast %d %a %a\n", rcb, (double)rb32.value, (double)rb32.error);
 
   HIP_OK(hipFree(x));
   HIP_OK(hipFree(y));
@@ -152,6 +170,9 @@ int main(void) {
   HIP_OK(hipFree(mws));
   HIP_OK(hipFree(outm));
   HIP_OK(hipFree(xws));
+  HIP_OK(hipFree(outb64));
+  HIP_OK(hipFree(outb32));
+  HIP_OK(hipFree(bws));
   HIP_OK(hipFree(outw));
   if (plan) twofold_seg_plan_destroy(plan);
   HIP_OK(hipStreamDestroy(st));

@@ -92,6 +92,13 @@ def test_native_client_matches_the_oracle():
         want = oracle.model_single("wide", x[a:], None, a % 2, lc.block_threads, lc.unroll,
                                    lc.grid_blocks)
         assert _pair(rows["multisumd_f64_%d" % v]) == (want[0], want[1]), v
+    # the mixed batch: its launch is the default of its largest item (the
+    # binary64 dot); each pair is the single call's with that launch
+    lc = _launch(0, 8, 1, 2, N)
+    for row, mode, a, b in (("batch_dot_f64_rigorous", "rigorous", x, y),
+                            ("batch_sum_f32_fast", "fast", xf, None)):
+        want = oracle.model_single(mode, a, b, mis, lc.block_threads, lc.unroll, lc.grid_blocks)
+        assert _pair(rows[row]) == (want[0], want[1]), row
     m = rows["monitor"]
     assert int(m[0]) == 0
     flags = monitor.flags(seg, np.diff(OFF), 0.0, np.float64)
