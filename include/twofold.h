@@ -289,7 +289,8 @@ int twofold_multidot_mixed_f32(const float* const* x, const float* const* y, con
  * pair (device twofold_f32_t or twofold_f64_t, by the data type). items is a
  * HOST array. Every item's pair is bitwise the one its single-vector call
  * (twofold_sum_* / twofold_dot_*) returns with the batch's launch; launch
- * NULL takes the default launch of the item that reads the most bytes. As in
+ * NULL takes the default launch of the item that reads the most bytes, with
+ * at most four vectors per lane a round (unroll <= 4). As in
  * the multi-vector calls, items of at most 64 MiB each run side by side,
  * longer ones in turn through one block set, and one combine kernel
  * finishes them all, so a batch pays the per-launch costs once.

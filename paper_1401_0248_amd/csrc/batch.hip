@@ -138,7 +138,11 @@ int resolve_batch(const twofold_batch_item_t* items, int64_t count,
   *max_bytes = best < 0 ? 0 : best;
   if (count == 0) return TWOFOLD_OK;
   const twofold_batch_item_t& m = items[bi];
-  return resolve_single(m.dtype, m.is_dot != 0, m.mode, m.n, launch, lc);
+  const int rc = resolve_single(m.dtype, m.is_dot != 0, m.mode, m.n, launch, lc);
+  // the batch kernel holds every form's code; above four vectors a round it
+  // spills, so a default launch takes at most four
+  if (!rc && !launch && lc->unroll > 4) lc->unroll = 4;
+  return rc;
 }
 
 template <int U>

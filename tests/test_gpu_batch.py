@@ -66,6 +66,19 @@ def test_batch_default_launch_long_items_in_turn():
         assert torch.equal(outs[v].view(torch.int8), one.view(torch.int8)), v
 
 
+def test_batch_default_launch_caps_the_unroll():
+    # the largest item, a binary32 sum of 2^26 elements, has a default launch
+    # of eight vectors a round; the batch takes at most four
+    n = 1 << 26
+    x = torch.empty(n, dtype=torch.float32, device="cuda:0").uniform_(-1, 1)
+    y = torch.empty(1000, dtype=torch.float64, device="cuda:0").uniform_(-1, 1)
+    d = tf.default_launch(0, 4, False, "rigorous", n)
+    lc = tf.Launch(d.block_threads, min(d.unroll, 4), d.grid_blocks, 0, 0)
+    outs = tf.batch([(x, None, "rigorous"), (y, y, "fast")])
+    assert torch.equal(outs[0].view(torch.int8), tf.sum(x, "rigorous", lc).view(torch.int8))
+    assert torch.equal(outs[1].view(torch.int8), tf.dot(y, y, "fast", lc).view(torch.int8))
+
+
 def test_batch_graph_replay():
     host, dev = _items(7, 24, 1 << 15)
     lc = launch(256, 2, 4)
