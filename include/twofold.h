@@ -122,8 +122,8 @@
  * preparation and holds nothing useful afterwards. Calls that may run at
  * the same time need separate workspaces. A single-vector call that runs
  * one block does not touch ws (it may then be NULL).
- * Kernels: a single-vector or multi-vector call is one kernel (one block)
- * or two (blocks, then the binary64 combine); a segmented call is the
+ * Kernels: a single-vector, multi-vector or batch call is one kernel (one
+ * block) or two (blocks, then the binary64 combine); a segmented call is the
  * tiling kernel (device offsets only), the tile kernel and the per-segment
  * combine kernel. Later kernels see earlier ones' results through the
  * stream order alone: no kernel waits on, or fences for, another block.
