@@ -8,8 +8,8 @@ rigorous dots run first, so no pair is re-read while it could still sit in
 the 256 MB last-level cache. Prints one JSON line.
 
 The dominant kernel is the batch (4.5 GiB per launch); its average duration
-is measured with HIP events on the launch stream during the timed steps and
-gives the roofline entry (algorithmic bytes / time vs 8 TB/s). Every dot is
+is measured with a pair of HIP events on the launch stream around the timed
+steps (a step is that launch alone) and gives the roofline entry (algorithmic bytes / time vs 8 TB/s). Every dot is
 checked bit for bit against its single-vector call with the same launch
 after the timed region, and the binary64 rigorous single calls are timed for
 reference. The CPU-baseline leg, the only part that runs the oracle, times
@@ -632,34 +632,29 @@ def main():
     with torch.cuda.graph(g, stream=cap):
         tf.batch(calls, outs=outs, ws=ws)
     stream = torch.cuda.current_stream(dev)
-    ev = []
-
-    def step(timed):
-        if timed:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            g.replay()
-            e1.record(stream)
-            ev.append((e0, e1))
-        else:
-            g.replay()
 
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
-        step(False)
+        g.replay()
     torch.cuda.synchronize()
+    # A step is nothing but the batch launch (and its combine kernel), so one
+    # pair of HIP events on the launch stream around the timed steps gives
+    # the average launch time; an event pair around every step would add its
+    # own gaps between the launches.
     log("timing %d steps" % args.steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    e0.record(stream)
     for _ in range(args.steps):
-        step(True)
+        g.replay()
+    e1.record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = 1e3 * elapsed / args.steps
     ndots = len(items)
     value = ndots * N * args.steps / elapsed / 1e9
-    launches_s = [a.elapsed_time(b) * 1e-3 for a, b in ev]
-    avg = sum(launches_s) / len(launches_s)
+    avg = e0.elapsed_time(e1) * 1e-3 / args.steps
     achieved = bytes_step / avg / 1e9
     # every result of the last timed step against the eager run, bit for bit
     repeatable = all(torch.equal(e.view(torch.int8), o.view(torch.int8))
