@@ -284,11 +284,14 @@ int twofold_multidot_mixed_f32(const float* const* x, const float* const* y, con
 /* ---- a mixed batch: up to 64 sums and dots of either data type and any
  * form in one launch ---------------------------------------------------------
  * Each item names its data (device pointers), its length, its data type (4
- * or 8), whether it is a dot, its mode (the modes whose results have the
- * data's type: TWOFOLD_WIDE and TWOFOLD_MIXED give EINVAL) and its output
- * pair (device twofold_f32_t or twofold_f64_t, by the data type). items is a
- * HOST array. Every item's pair is bitwise the one its single-vector call
- * (twofold_sum_* / twofold_dot_*) returns with the batch's launch; launch
+ * or 8), whether it is a dot, its mode (any mode its single-vector calls
+ * take) and its output pair: a device twofold_f32_t for binary32 data, a
+ * twofold_f64_t for binary64 data and for TWOFOLD_WIDE and TWOFOLD_MIXED.
+ * items is a HOST array. Every item's pair is bitwise the one its
+ * single-vector call (twofold_sum_* / twofold_dot_*, twofold_sumd_* /
+ * twofold_dotd_*, twofold_{sum,dot}_mixed_f32) returns with the batch's
+ * launch; a batch with a TWOFOLD_WIDE or TWOFOLD_MIXED item runs a kernel
+ * that holds those forms too. launch
  * NULL takes the default launch of the item that reads the most bytes, with
  * at most four vectors per lane a round (unroll <= 4). As in
  * the multi-vector calls, items of at most 64 MiB each run side by side,
@@ -299,11 +302,11 @@ int twofold_multidot_mixed_f32(const float* const* x, const float* const* y, con
 typedef struct {
   const void* x;   /* device data, n elements of dtype bytes */
   const void* y;   /* device data for a dot; ignored for a sum */
-  void* out;       /* device output pair of the data's type */
+  void* out;       /* device output pair: the data's type, binary64 for WIDE, MIXED */
   int64_t n;
   int32_t dtype;   /* 4: binary32, 8: binary64 */
   int32_t is_dot;  /* 0: sum of x, 1: dot of x and y */
-  int32_t mode;    /* TWOFOLD_PLAIN ... TWOFOLD_RIGOROUS_ROUNDED, not WIDE or MIXED */
+  int32_t mode;    /* any mode of the single-vector calls (MIXED: binary32 data) */
   int32_t reserved;
 } twofold_batch_item_t;
 size_t twofold_workspace_bytes_batch(const twofold_batch_item_t* items, int64_t count,

@@ -258,11 +258,12 @@ MAX_BATCH = 64  # items per batch call
 
 
 def batch(items, launch=None, outs=None, ws=None):
-    """Up to 64 sums and dots of either data type and any mode with results
-    of the data's type, in one launch (twofold_batch). items: (x, y, mode)
-    tuples, y None for a sum. Returns one tensor([value, error]) per item,
-    bitwise the sum()/dot() of that item with the batch's launch (default:
-    the launch of the item that reads the most bytes)."""
+    """Up to 64 sums and dots of either data type and any mode in one launch
+    (twofold_batch). items: (x, y, mode) tuples, y None for a sum. Returns
+    one tensor([value, error]) per item (float64 for "wide" and "mixed"),
+    bitwise that item's single call (sum/dot, sumd/dotd, sum_mixed/dot_mixed)
+    with the batch's launch (default: the launch of the item that reads the
+    most bytes, at most four vectors a round)."""
     L = _lib.load()
     items = list(items)
     count = len(items)
@@ -277,7 +278,9 @@ def batch(items, launch=None, outs=None, ws=None):
         _check_data(*([x] if y is None else [x, y]))
         if x.device != dev:
             raise ValueError("twofold: all items must be on one device")
-        o = _out(None if outs is None else outs[v], 1, x.dtype, dev, (2,))
+        m = mode_id(mode)
+        odt = torch.float64 if m in (WIDE, MIXED) else x.dtype
+        o = _out(None if outs is None else outs[v], 1, odt, dev, (2,))
         res.append(o)
         arr[v].x = x.data_ptr()
         arr[v].y = y.data_ptr() if y is not None else None
@@ -285,7 +288,7 @@ def batch(items, launch=None, outs=None, ws=None):
         arr[v].n = x.numel()
         arr[v].dtype = x.element_size()
         arr[v].is_dot = int(y is not None)
-        arr[v].mode = mode_id(mode)
+        arr[v].mode = m
     lp = _launch_ptr(launch)
     need = L.twofold_workspace_bytes_batch(ctypes.cast(arr, ctypes.c_void_p), count, lp)
     if need == 0:

@@ -1,5 +1,6 @@
 // batch.hip: a mixed batch of sums and dots in one launch (twofold_batch in
-// include/twofold.h). Items may differ in data type, operation and form;
+// include/twofold.h). Items may differ in data type, operation and form
+// (every form, the binary64-result ones included);
 // each is reduced exactly as its single-vector call with the batch's launch
 // (steps 1-8), so its pair is that call's, bit for bit. The per-item form is
 // a uniform branch at the item's start: every block takes the same path.
@@ -75,6 +76,49 @@ batch_kernel(const BatchArgs args, int count, double* __restrict__ part) {
   }
 }
 
+// Items with binary64 results: the wider accumulator (binary64 for binary32
+// data, double-word for binary64 data) and the mixed form (binary32 data).
+// A kernel of their own, so that batches of same-type forms keep the leaner
+// kernel above.
+template <bool DOT, bool YV, int U>
+__device__ __forceinline__ void batch_item_wide(const BatchEntry& b, int64_t kind, double* part) {
+  if (kind & 1) {
+    single_block<double, double, kDoubleDouble, DOT, YV, U>(
+        static_cast<const double*>(b.x), static_cast<const double*>(b.y), b.n, part, b.out, 0);
+  } else if ((kind >> 3) == kMixed) {
+    single_block<float, double, kMixed, DOT, YV, U>(
+        static_cast<const float*>(b.x), static_cast<const float*>(b.y), b.n, part, b.out, 0);
+  } else {
+    single_block<float, double, kWide, DOT, YV, U>(
+        static_cast<const float*>(b.x), static_cast<const float*>(b.y), b.n, part, b.out, 0);
+  }
+}
+
+template <int U>
+__global__ void __launch_bounds__(1024)
+batch_kernel_wide(const BatchArgs args, int count, double* __restrict__ part) {
+  for (int v = blockIdx.y; v < count; v += gridDim.y) {
+    const BatchEntry& b = args.e[v];
+    double* p = part + 2 * static_cast<int64_t>(v) * gridDim.x;
+    const int mode = static_cast<int>(b.kind >> 3);
+    if (mode == kWide || mode == kMixed) {
+      if (b.kind & 2) {
+        if (b.kind & 4)
+          batch_item_wide<true, true, U>(b, b.kind, p);
+        else
+          batch_item_wide<true, false, U>(b, b.kind, p);
+      } else {
+        batch_item_wide<false, true, U>(b, b.kind, p);
+      }
+    } else if (b.kind & 1) {
+      batch_by_op<double, U>(b, b.kind, p);
+    } else {
+      batch_by_op<float, U>(b, b.kind, p);
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void batch_pass2_by_mode(const BatchEntry& b, const double2* pairs,
                                                     int nparts) {
@@ -84,7 +128,16 @@ __device__ __forceinline__ void batch_pass2_by_mode(const BatchEntry& b, const d
     case kRigorous: pass2_block<T, kRigorous>(pairs, nparts, b.out, 0); break;
     case kKahan: pass2_block<T, kKahan>(pairs, nparts, b.out, 0); break;
     case kFastRounded: pass2_block<T, kFastRounded>(pairs, nparts, b.out, 0); break;
-    default: pass2_block<T, kRigorousRounded>(pairs, nparts, b.out, 0); break;
+    case kRigorousRounded: pass2_block<T, kRigorousRounded>(pairs, nparts, b.out, 0); break;
+    case kWide:
+      if constexpr (sizeof(T) == 4)
+        pass2_block<T, kWide>(pairs, nparts, b.out, 0);
+      else
+        pass2_block<T, kDoubleDouble>(pairs, nparts, b.out, 0);
+      break;
+    default:
+      if constexpr (sizeof(T) == 4) pass2_block<T, kMixed>(pairs, nparts, b.out, 0);
+      break;
   }
 }
 
@@ -111,9 +164,7 @@ namespace {
 // each), as in the multi-vector calls; otherwise one set walks them in turn.
 constexpr int64_t kBatchSideBytes = int64_t(1) << 26;
 
-bool batch_mode_ok(int dtype, bool dot, int mode) {
-  return mode_ok(dtype, dot, mode) && mode != kWide && mode != kMixed;
-}
+bool batch_mode_ok(int dtype, bool dot, int mode) { return mode_ok(dtype, dot, mode); }
 
 int64_t item_bytes(const twofold_batch_item_t& it) {
   return it.n * it.dtype * (it.is_dot ? 2 : 1);
@@ -146,10 +197,13 @@ int resolve_batch(const twofold_batch_item_t* items, int64_t count,
 }
 
 template <int U>
-int launch_batch_u(const BatchArgs& a, int count, int sets, const twofold_launch_t& lc,
+int launch_batch_u(const BatchArgs& a, int count, int sets, bool wide, const twofold_launch_t& lc,
                    double* part, hipStream_t st) {
-  batch_kernel<U><<<dim3(lc.grid_blocks, unsigned(sets)), dim3(lc.block_threads), 0, st>>>(
-      a, count, part);
+  const dim3 grid(lc.grid_blocks, unsigned(sets)), block(lc.block_threads);
+  if (wide)
+    batch_kernel_wide<U><<<grid, block, 0, st>>>(a, count, part);
+  else
+    batch_kernel<U><<<grid, block, 0, st>>>(a, count, part);
   if (launch_status()) return TWOFOLD_EHIP;
   if (lc.grid_blocks > 1) {
     batch_pass2_kernel<<<dim3(unsigned(count)), dim3(kPass2Lanes), 0, st>>>(a, part,
@@ -179,14 +233,16 @@ int twofold_batch(const twofold_batch_item_t* items, int64_t count,
   const int rc = resolve_batch(items, count, launch, &lc, &max_bytes);
   if (rc) return rc;
   BatchArgs a;
+  bool wide = false;  // any item with binary64 results: the kernel that holds them
   for (int64_t v = 0; v < count; v++) {
     const twofold_batch_item_t& it = items[v];
     const bool dot = it.is_dot != 0;
     // data pointers may be NULL only when there is no data
     if (!it.out || (!it.x && it.n > 0) || (dot && !it.y && it.n > 0)) return TWOFOLD_EINVAL;
     if (!elem_aligned(it.x, it.dtype) || (dot && !elem_aligned(it.y, it.dtype)) ||
-        !elem_aligned(it.out, it.dtype))
+        !elem_aligned(it.out, out_f64(it.dtype, it.mode) ? 8 : 4))
       return TWOFOLD_EALIGN;
+    if (it.mode == kWide || it.mode == kMixed) wide = true;
     const bool yv = !dot || ((reinterpret_cast<uintptr_t>(it.y) -
                               reinterpret_cast<uintptr_t>(it.x)) & 15u) == 0;
     a.e[v].x = it.x;
@@ -205,10 +261,10 @@ int twofold_batch(const twofold_batch_item_t* items, int64_t count,
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int c = int(count);
   switch (lc.unroll) {
-    case 1: return launch_batch_u<1>(a, c, sets, lc, part, st);
-    case 2: return launch_batch_u<2>(a, c, sets, lc, part, st);
-    case 4: return launch_batch_u<4>(a, c, sets, lc, part, st);
-    default: return launch_batch_u<8>(a, c, sets, lc, part, st);
+    case 1: return launch_batch_u<1>(a, c, sets, wide, lc, part, st);
+    case 2: return launch_batch_u<2>(a, c, sets, wide, lc, part, st);
+    case 4: return launch_batch_u<4>(a, c, sets, wide, lc, part, st);
+    default: return launch_batch_u<8>(a, c, sets, wide, lc, part, st);
   }
 }
 

@@ -331,8 +331,7 @@ def test_batch_argument_checks():
     assert L.twofold_batch(items(ok), -1, None, ws, big, None) == EINVAL
     assert L.twofold_batch(None, 2, None, ws, big, None) == EINVAL
     assert L.twofold_batch(None, 0, None, ws, big, None) == 0  # nothing to do
-    for bad in ((0x10000, 0x20000, 0x30000, 100, 8, 1, 3),   # wide: binary64 rows elsewhere
-                (0x10000, 0x20000, 0x30000, 100, 4, 1, 7),   # mixed
+    for bad in ((0x10000, 0x20000, 0x30000, 100, 8, 1, 7),   # mixed: binary32 data only
                 (0x10000, 0, 0x30000, 100, 8, 0, 5),         # rounded-product sum
                 (0x10000, 0x20000, 0x30000, 100, 2, 1, 2),   # dtype
                 (0x10000, 0x20000, 0x30000, -1, 8, 1, 2),    # length
@@ -341,7 +340,8 @@ def test_batch_argument_checks():
                 (None, 0x20000, 0x30000, 100, 8, 1, 2),      # x
                 (0x10000, None, 0x30000, 100, 8, 1, 2)):     # y of a dot
         assert L.twofold_batch(items(ok, bad), 2, None, ws, big, None) == EINVAL, bad
-    for mis in ((0x10004, 0x20000, 0x30000, 100, 8, 1, 2), (0x10000, 0x20000, 0x30004, 100, 8, 1, 2)):
+    for mis in ((0x10004, 0x20000, 0x30000, 100, 8, 1, 2), (0x10000, 0x20000, 0x30004, 100, 8, 1, 2),
+                (0x10000, 0x20000, 0x30004, 100, 4, 1, 7)):  # mixed: binary64 output pair
         assert L.twofold_batch(items(ok, mis), 2, None, ws, big, None) == EALIGN, mis
     # workspace: count times the single-vector one of the largest item's launch
     two = items((0x10000, 0x20000, 0x30000, 1 << 24, 8, 1, 2), (0x10000, 0, 0x30000, 5, 4, 0, 1))
@@ -349,5 +349,7 @@ def test_batch_argument_checks():
     one = L.twofold_workspace_bytes_single(8, 1, 2, 1 << 24, None)
     assert need >= 2 * (one - 255)
     assert L.twofold_batch(two, 2, None, ws, need - 256, None) == EWORKSPACE
-    assert L.twofold_workspace_bytes_batch(items((0x10000, 0x20000, 0x30000, 100, 8, 1, 3)), 1,
+    assert L.twofold_workspace_bytes_batch(items((0x10000, 0x20000, 0x30000, 100, 8, 1, 7)), 1,
                                            None) == 0
+    assert L.twofold_workspace_bytes_batch(items((0x10000, 0x20000, 0x30000, 100, 4, 1, 3)), 1,
+                                           None) > 0  # binary64 accumulator of binary32 data

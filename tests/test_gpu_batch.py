@@ -1,5 +1,5 @@
 """GPU parity of the mixed batch (twofold_batch): items of both data types,
-sums and dots, every mode with results of the data's type, ragged lengths
+sums and dots, every mode (the binary64-result ones too), ragged lengths
 and alignments. Every item's pair is bitwise the order model's
 single-vector result under the batch's launch and bitwise the single call
 with that launch, whether the items run side by side or in turn."""
@@ -17,13 +17,15 @@ MODES_SUM = ("plain", "fast", "rigorous", "kahan")
 MODES_DOT = MODES_SUM + ("fast_rounded", "rigorous_rounded")
 
 
-def _items(seed, count, max_len):
+def _items(seed, count, max_len, wide=False):
     rng = np.random.default_rng(seed)
     host, dev = [], []
     for v in range(count):
         dtype = (np.float32, np.float64)[rng.integers(0, 2)]
         dot = bool(rng.integers(0, 2))
         mode = (MODES_DOT if dot else MODES_SUM)[rng.integers(0, 6 if dot else 4)]
+        if wide and rng.random() < 0.4:  # the binary64-result forms
+            mode = "mixed" if (dtype == np.float32 and rng.random() < 0.5) else "wide"
         n = int(rng.choice([0, 1, 3, 17, 1000, 4097, int(rng.integers(1, max_len))]))
         x = (rng.standard_normal(n) * np.exp2(rng.integers(-12, 12, n))).astype(dtype)
         y = rng.standard_normal(n).astype(dtype)
@@ -35,9 +37,17 @@ def _items(seed, count, max_len):
     return host, dev
 
 
-@pytest.mark.parametrize("seed", range(4))
-def test_batch_bitwise_vs_model_and_single_calls(seed):
-    host, dev = _items(100 + seed, 40, 1 << 17)
+def _single(xd, yd, mode, lc):
+    if mode == "wide":
+        return tf.dotd(xd, yd, lc) if yd is not None else tf.sumd(xd, lc)
+    if mode == "mixed":
+        return tf.dot_mixed(xd, yd, lc) if yd is not None else tf.sum_mixed(xd, lc)
+    return tf.dot(xd, yd, mode, lc) if yd is not None else tf.sum(xd, mode, lc)
+
+
+@pytest.mark.parametrize("seed,wide", [(s, w) for s in range(4) for w in (False, True)])
+def test_batch_bitwise_vs_model_and_single_calls(seed, wide):
+    host, dev = _items(100 + seed, 40, 1 << 17, wide)
     for bt, u, gb in ((256, 1, 1), (256, 4, 7), (512, 2, 3), (128, 8, 33)):
         lc = launch(bt, u, gb)
         outs = tf.batch(dev, lc)
@@ -45,8 +55,8 @@ def test_batch_bitwise_vs_model_and_single_calls(seed):
             want = oracle.model_single(mode, x, y, mis, bt, u, gb)
             got = outs[v].double().cpu().numpy()
             assert same_bits(tuple(got), want), (seed, v, mode, x.dtype, x.size, bt, u, gb)
-            one = tf.dot(xd, yd, mode, lc) if yd is not None else tf.sum(xd, mode, lc)
-            assert torch.equal(outs[v].view(torch.int8), one.view(torch.int8)), (seed, v)
+            assert torch.equal(outs[v].view(torch.int8), _single(xd, yd, mode, lc).view(torch.int8)), \
+                (seed, v)
 
 
 def test_batch_default_launch_long_items_in_turn():
@@ -103,7 +113,7 @@ def test_batch_graph_replay():
 def test_batch_rejects_bad_items():
     x = torch.zeros(100, dtype=torch.float32, device="cuda:0")
     with pytest.raises(tf.TwofoldError):
-        tf.batch([(x, x, "wide")])
+        tf.batch([(x.double(), x.double(), "mixed")])  # the mixed form: binary32 data
     with pytest.raises(tf.TwofoldError):
         tf.batch([(x, None, "fast_rounded")])
     with pytest.raises(ValueError):
