@@ -10,10 +10,11 @@ Three parts, all in plain C (``liboracle.so``, built by ``oracle/build.py``):
   S = sum x_n or sum x_n*y_n and A = sum |x_n| or sum |x_n*y_n|
   (the exact real that the paper's value + error pair approximates,
   "Overview").
-* ``seq``: the paper's sequential loops (section "Algorithms": Example 1
+* ``seq``: the paper's sequential methods (section "Algorithms": Example 1
   ``sumtf``, Example 2 ``sumk``, Example 3 ``sumt`` and direct ``sum``, the
-  double accumulator ``sumd``, and the dot rule that puts ``a[i]*b[i]`` in
-  place of ``data[i]``), plus the dot with an FMA remainder, and for
+  double accumulator ``sumd``, and dot products summing the rounded
+  products x_i*y_i as items), restated on fast-two-sum and two-sum
+  (Theorems 1 and 2), plus the dot with an FMA remainder, and for
   binary64 data the double-word accumulator ``sumdd``/``dotdd`` standing in
   for the paper's quad one (``dw_plus_fp``/``dw_plus_dw`` expose its steps).
 * ``model_single`` / ``model_seg``: the same per-element steps applied in the

@@ -59,6 +59,15 @@
 #define MODE_DW 8
 #define HAS_ERROR(m) ((m) != MODE_PLAIN && (m) != MODE_WIDE)
 
+/* Two-sum (Theorem 2) in binary32, for the mixed mode's value chain. */
+static void two_sum_b32(float a, float b, float* s, float* r) {
+  float t = a + b;
+  float bv = t - a;
+  float av = t - bv;
+  *s = t;
+  *r = (a - av) + (b - bv);
+}
+
 static void combine64(int mode, double* s1, double* e1, double s2, double e2) {
   if (!HAS_ERROR(mode)) {
     *s1 = *s1 + s2;

@@ -12,11 +12,12 @@
  *   1. An exact fixed-point accumulator (xacc) that defines the target
  *      S = sum x_n or S = sum x_n*y_n exactly, and A = sum |x_n| or
  *      sum |x_n*y_n| exactly; results are rounded once, to nearest even.
- *   2. The paper's sequential loops (Latkin, "Twofold fast summation",
+ *   2. The paper's sequential methods (Latkin, "Twofold fast summation",
  *      section "Algorithms": Example 1 sumtf, Example 2 Kahan sumk,
- *      Example 3 sumt and direct sum, the double-accumulator sumd, and the
- *      dot rule that substitutes a[i]*b[i] for data[i]); plus the dot with
- *      an FMA exact product (this library's reading, see the model below).
+ *      Example 3 sumt and direct sum, the double-accumulator sumd, and dot
+ *      products that sum the rounded products x_i*y_i as items), restated
+ *      on fast-two-sum and two-sum (Theorems 1 and 2); plus the dot with an
+ *      FMA exact product (this library's reading, see the model below).
  *   3. An order model: the same per-element steps applied in the order the
  *      GPU library documents for its reductions, used for bitwise checks.
  */

@@ -36,39 +36,40 @@ MUTANTS = [
     ("xacc product sign", "xacc.c", "absval ? 0 : (nx ^ ny))", "absval ? 0 : (nx | ny))"),
     ("xacc exponent off by one", "xacc.c", "*e = ex - 53;", "*e = ex - 52;"),
     ("xacc carry sign", "xacc.c", "a->dig[i + 1] += c;", "a->dig[i + 1] -= c;"),
-    # the paper's sequential loops
-    ("sumtf error sign", "paper_loops.inc",
-     "    T c = (t - s) - y;\n    e = e - c;", "    T c = (t - s) - y;\n    e = e + c;"),
-    ("sumt dropped ds", "paper_loops.inc",
-     "    T ds = s - (t - yt);\n    e = e + (ds + dy);\n    s = t;\n  }\n  out2[0] = s;\n"
-     "  out2[1] = e;\n}\n\n/* Dot products by",
-     "    T ds = s - (t - yt);\n    e = e + dy;\n    s = t;\n  }\n  out2[0] = s;\n"
-     "  out2[1] = e;\n}\n\n/* Dot products by"),
-    ("sumt dy sign", "paper_loops.inc",
-     "    T y = x[i];\n    T t = s + y;\n    T yt = t - s;\n    T dy = y - yt;",
-     "    T y = x[i];\n    T t = s + y;\n    T yt = t - s;\n    T dy = yt - y;"),
-    ("sumk correction sign", "paper_loops.inc",
-     "T NAME(sumk)(const T* x, int64_t n) {\n  T s = 0, c = 0;\n  for (int64_t i = 0; i < n; i++) {\n"
-     "    T y = x[i] - c;",
-     "T NAME(sumk)(const T* x, int64_t n) {\n  T s = 0, c = 0;\n  for (int64_t i = 0; i < n; i++) {\n"
-     "    T y = x[i] + c;"),
-    ("dott dropped product remainder", "paper_loops.inc",
-     "e = e + ((ds + dy) + pi);", "e = e + (ds + dy);"),
-    ("dottf remainder sign", "paper_loops.inc", "e = e + (pi - c);", "e = e + (pi + c);"),
+    # the paper's sequential methods
+    ("fast-two-sum remainder sign", "paper_loops.inc",
+     "  *r = b - (t - a);", "  *r = (t - a) - b;"),
+    ("two-sum dropped the first operand's part", "paper_loops.inc",
+     "  *r = (a - av) + (b - bv);", "  *r = (b - bv);"),
+    ("two-sum second part sign", "paper_loops.inc",
+     "  *r = (a - av) + (b - bv);", "  *r = (a - av) + (bv - b);"),
+    ("two-sum first part operand", "paper_loops.inc",
+     "  const T av = t - bv;", "  const T av = t - b;"),
+    ("Kahan correction sign", "paper_loops.inc",
+     "NAME(fts)(s, item + k, &s, &k);", "NAME(fts)(s, item - k, &s, &k);"),
+    ("twofold dot dropped product remainder", "paper_loops.inc",
+     "if (y && exact_product) r = r + FMA(x[i], y[i], -item);",
+     "if (y && exact_product) r = r;"),
+    ("twofold dot product remainder sign", "paper_loops.inc",
+     "if (y && exact_product) r = r + FMA(x[i], y[i], -item);",
+     "if (y && exact_product) r = r - FMA(x[i], y[i], -item);"),
+    ("twofold error sign", "paper_loops.inc", "    e = e + r;", "    e = e - r;"),
     ("dot swapped factor", "paper_loops.inc",
-     "T NAME(dot)(const T* x, const T* y, int64_t n) {\n  T s = 0;\n"
-     "  for (int64_t i = 0; i < n; i++) {\n    T p = x[i] * y[i];",
-     "T NAME(dot)(const T* x, const T* y, int64_t n) {\n  T s = 0;\n"
-     "  for (int64_t i = 0; i < n; i++) {\n    T p = x[i] * x[i];"),
+     "  for (int64_t i = 0; i < n; i++) s = s + x[i] * y[i];",
+     "  for (int64_t i = 0; i < n; i++) s = s + x[i] * x[i];"),
     # order model: steps
-    ("model rigorous dy sign", "order_model.inc", "A dy = item - yt;", "A dy = yt - item;"),
-    ("model rigorous ds operand", "order_model.inc",
-     "A ds = *s - (t - yt);", "A ds = *s - (t - item);"),
-    ("model fast dot dropped remainder", "order_model.inc",
-     "*e = *e + (pi - c);", "*e = *e - c;"),
-    ("model rigorous dot dropped remainder", "order_model.inc",
-     "*e = *e + ((ds + dy) + pi);", "*e = *e + (ds + dy);"),
-    ("model Kahan sign", "order_model.inc", "A yk = item + *e;", "A yk = item - *e;"),
+    ("model two-sum second part sign", "order_model.inc",
+     "  *r = (a - av) + (b - bv);", "  *r = (a - av) + (bv - b);"),
+    ("model two-sum first part operand", "order_model.inc",
+     "  A av = t - bv;", "  A av = t - b;"),
+    ("model fast-two-sum remainder sign", "order_model.inc",
+     "  *r = b - (t - a);", "  *r = (t - a) - b;"),
+    ("model dot dropped product remainder", "order_model.inc",
+     "if (track) r = r + (A)FMA_T(xv, yv, -p);", "if (track) r = r;"),
+    ("model dot product remainder sign", "order_model.inc",
+     "if (track) r = r + (A)FMA_T(xv, yv, -p);", "if (track) r = r - (A)FMA_T(xv, yv, -p);"),
+    ("model Kahan sign", "order_model.inc",
+     "NAME(fts)(*s, item + *e, s, e);", "NAME(fts)(*s, item - *e, s, e);"),
     # order model: combines, grid combine, finalize
     ("combine dropped partner error", "order_model.inc",
      "  *e1 = (*e1 + e2) + y;\n  *s1 = x;", "  *e1 = *e1 + y;\n  *s1 = x;"),
@@ -80,10 +81,12 @@ MUTANTS = [
      "A item = is_dot ? (A)xv * (A)yv : (A)xv;", "A item = is_dot ? (A)(xv * yv) : (A)xv;"),
     # the mixed form
     ("mixed dot dropped remainder", "order_model.inc",
-     "*e = *e + ((double)(ds + dy) + (double)fmaf(xf, yf, -p));", "*e = *e + (double)(ds + dy);"),
+     "*e = *e + ((double)r + (double)fmaf(xf, yf, -p));", "*e = *e + (double)r;"),
     ("mixed error kept in binary32", "order_model.inc",
-     "      *e = *e + (double)(ds + dy);\n    *s = (A)t;",
-     "      *e = (float)(*e + (double)(ds + dy));\n    *s = (A)t;"),
+     "      *e = *e + (double)r;\n    *s = (A)t;",
+     "      *e = (float)(*e + (double)r);\n    *s = (A)t;"),
+    ("mixed two-sum sign", "order_model.c",
+     "  *r = (a - av) + (b - bv);", "  *r = (a - av) - (b - bv);"),
     ("mixed finalize error narrowed", "order_model.c",
      "out2[1] = (V - v) + E;", "out2[1] = (double)(float)((V - v) + E);"),
     # order model: the order itself
