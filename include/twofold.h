@@ -164,7 +164,10 @@ enum {
   TWOFOLD_EWORKSPACE = -2, /* workspace missing or too small             */
   TWOFOLD_EHIP = -3,       /* a HIP call failed (launch or runtime)      */
   TWOFOLD_EALIGN = -4,     /* a data pointer is not element-aligned      */
-  TWOFOLD_EOFFSETS = -5    /* segment offsets not non-decreasing from 0.. */
+  TWOFOLD_EOFFSETS = -5,   /* segment offsets not non-decreasing from 0.. */
+  TWOFOLD_ENOTUNED = -6,   /* twofold_tuned_launch: no measured row      */
+  TWOFOLD_ECAPTURE = -7    /* a stream capture is under way: plan
+                              creation (synchronous) is not allowed      */
 };
 
 /* Launch configuration. Zero fields take the tuned default.
@@ -187,6 +190,16 @@ typedef struct {
  * nseg segments). dtype 4 or 8; mode TWOFOLD_*. */
 int twofold_default_launch(int kind, int dtype, int is_dot, int mode, int64_t n, int64_t nseg,
                            twofold_launch_t* out);
+
+/* The same default, and whether it was measured: the launch table holds
+ * rows measured by the autotuner per (kind, dtype, operation, mode, size
+ * bucket). Returns TWOFOLD_OK when a row of this very (kind, dtype, is_dot,
+ * mode) covers n, TWOFOLD_ENOTUNED when the default is borrowed (from the
+ * rigorous mode's rows of the same data type and operation, or the
+ * built-in shape); *out is filled either way. Other errors as
+ * twofold_default_launch. */
+int twofold_tuned_launch(int kind, int dtype, int is_dot, int mode, int64_t n, int64_t nseg,
+                         twofold_launch_t* out);
 
 /* Workspace size for a single-vector call, and for a segmented call with
  * nseg segments over n_total elements. launch NULL: the default. */
@@ -293,7 +306,8 @@ int twofold_multidot_mixed_f32(const float* const* x, const float* const* y, con
  * launch; a batch with a TWOFOLD_WIDE or TWOFOLD_MIXED item runs a kernel
  * that holds those forms too. launch
  * NULL takes the default launch of the item that reads the most bytes, with
- * at most four vectors per lane a round (unroll <= 4). As in
+ * at most four vectors per lane a round (unroll <= 4) when that launch's
+ * blocks have more than 512 threads. As in
  * the multi-vector calls, items of at most 64 MiB each run side by side,
  * longer ones in turn through one block set, and one combine kernel
  * finishes them all, so a batch pays the per-launch costs once.
@@ -313,6 +327,7 @@ size_t twofold_workspace_bytes_batch(const twofold_batch_item_t* items, int64_t 
                                      const twofold_launch_t* launch);
 int twofold_batch(const twofold_batch_item_t* items, int64_t count,
                   const twofold_launch_t* launch, void* ws, size_t ws_bytes, void* stream);
+
 
 /* ---- segmented (CSR) batches: nseg pairs into out[0..nseg) ---------------
  * offsets: device int64[nseg + 1], non-decreasing, offsets[0] >= 0 and
@@ -359,8 +374,12 @@ int twofold_segdot_mixed_f32(const float* x, const float* y, int64_t n_total,
  * create: validates offsets_host (host int64[nseg+1], offsets[0] = 0,
  * non-decreasing), builds the tile table and copies offsets and table to
  * device memory owned by the plan, with the plan's per-segment completion
- * (synchronous; not capturable). The workspace of an execute holds the
- * pairs of the tiles of multi-tile segments.
+ * (synchronous; not capturable). It returns TWOFOLD_ECAPTURE, and makes no
+ * allocation or copy, when it finds a stream capture under way: on the
+ * legacy default stream's view (a capture on any blocking stream), or
+ * reported by the allocator (a global-mode capture on any stream). Create
+ * plans before capturing; their executes are capturable. The workspace of
+ * an execute holds the pairs of the tiles of multi-tile segments.
  * dtype 4 or 8; mode TWOFOLD_* (ROUNDED forms only for dots).
  * execute: the tile kernel (persistent waves) and the combine kernel on
  * stream, no host work in between; out is twofold_f64_t[nseg] for binary64
@@ -404,10 +423,14 @@ int twofold_monitor(int dtype, const void* pairs, int64_t count, const int64_t* 
 
 /* ---- instruments ----------------------------------------------------------
  * Memory-only probe (the paper's read1/read2, section "Memory reading"):
- * streams x (and y, if not NULL), nbytes each, with 16-byte loads in the
- * single-vector lane order of launch (block_threads, unroll, grid_blocks;
- * every field required), and ORs all loaded bits together. x, y 16-byte
- * aligned, nbytes a multiple of 16; sink: device uint64[grid_blocks].   */
+ * streams x (and y, if not NULL), nbytes each, through the single-vector
+ * sum's (dot's) own lane loop for launch (block_threads, unroll 1, 2, 4 or
+ * 8, grid_blocks; every field required): the same 16-byte loads in the same
+ * lane order, rounds and loads ahead, with the summation step replaced by a
+ * bit-OR of the loaded 32-bit words. sink[b] (device uint64[grid_blocks])
+ * receives the OR of every word block b loaded. x, y 16-byte aligned,
+ * nbytes a multiple of 16. Its rate bounds what the reduction kernels can
+ * stream with the same launch.                                          */
 int twofold_probe_read(const void* x, const void* y, int64_t nbytes, const twofold_launch_t* launch,
                        uint64_t* sink, void* stream);
 /* Compute-only probe (the paper's p-functions, section "Purely

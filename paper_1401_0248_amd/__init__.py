@@ -21,7 +21,7 @@ __all__ = [
     "sum", "dot", "sumd", "dotd", "sum_mixed", "dot_mixed", "multisum", "multidot", "segsum",
     "segdot", "SegPlan",
     "Launch", "monitor",
-    "TwofoldError", "workspace", "default_launch", "probe_read", "probe_compute",
+    "TwofoldError", "workspace", "default_launch", "tuned_launch", "probe_read", "probe_compute",
     "FLAG_ERROR", "FLAG_LENGTH", "FLAG_NONFINITE",
     "PLAIN", "FAST", "RIGOROUS", "WIDE", "KAHAN", "FAST_ROUNDED", "RIGOROUS_ROUNDED", "MIXED",
     "mode_id",
@@ -110,6 +110,18 @@ def default_launch(kind, dtype, is_dot, mode, n, nseg=0):
           _lib.load().twofold_default_launch(kind, dtype, int(is_dot), mode_id(mode), n, nseg,
                                              ctypes.byref(lc)))
     return lc
+
+
+def tuned_launch(kind, dtype, is_dot, mode, n, nseg=0):
+    """(launch, measured): the default launch, and whether the autotuner
+    measured a row of its own for this configuration (twofold_tuned_launch;
+    False when the default is borrowed from another mode or built in)."""
+    lc = Launch()
+    rc = _lib.load().twofold_tuned_launch(kind, dtype, int(is_dot), mode_id(mode), n, nseg,
+                                          ctypes.byref(lc))
+    if rc not in (_lib.OK, _lib.ENOTUNED):
+        check("twofold_tuned_launch", rc)
+    return lc, rc == _lib.OK
 
 
 def _single(fn, x, y, mode, launch, out, ws, out_dtype):
@@ -263,8 +275,23 @@ def batch(items, launch=None, outs=None, ws=None):
     one tensor([value, error]) per item (float64 for "wide" and "mixed"),
     bitwise that item's single call (sum/dot, sumd/dotd, sum_mixed/dot_mixed)
     with the batch's launch (default: the launch of the item that reads the
-    most bytes, at most four vectors a round)."""
+    most bytes, at most four vectors a round when its blocks have more than
+    512 threads)."""
     L = _lib.load()
+    arr, count, res, dev = _batch_items(items, outs)
+    lp = _launch_ptr(launch)
+    need = L.twofold_workspace_bytes_batch(ctypes.cast(arr, ctypes.c_void_p), count, lp)
+    if need == 0:
+        raise TwofoldError("twofold_workspace_bytes_batch", _lib.EINVAL)
+    if ws is None:
+        ws = workspace(need, dev)
+    check("twofold_batch", L.twofold_batch(ctypes.cast(arr, ctypes.c_void_p), count, lp,
+                                           ctypes.c_void_p(ws.ptr), ws.nbytes, _stream_ptr(dev)))
+    return res
+
+
+def _batch_items(items, outs):
+    """The twofold_batch_item_t array of a batch, and its output tensors."""
     items = list(items)
     count = len(items)
     if not 1 <= count <= MAX_BATCH:
@@ -289,15 +316,7 @@ def batch(items, launch=None, outs=None, ws=None):
         arr[v].dtype = x.element_size()
         arr[v].is_dot = int(y is not None)
         arr[v].mode = m
-    lp = _launch_ptr(launch)
-    need = L.twofold_workspace_bytes_batch(ctypes.cast(arr, ctypes.c_void_p), count, lp)
-    if need == 0:
-        raise TwofoldError("twofold_workspace_bytes_batch", _lib.EINVAL)
-    if ws is None:
-        ws = workspace(need, dev)
-    check("twofold_batch", L.twofold_batch(ctypes.cast(arr, ctypes.c_void_p), count, lp,
-                                           ctypes.c_void_p(ws.ptr), ws.nbytes, _stream_ptr(dev)))
-    return res
+    return arr, count, res, dev
 
 
 def sum_mixed(x, launch=None, out=None, ws=None):

@@ -9,7 +9,7 @@ import os
 
 from . import build as _build
 
-OK, EINVAL, EWORKSPACE, EHIP, EALIGN, EOFFSETS = 0, -1, -2, -3, -4, -5
+OK, EINVAL, EWORKSPACE, EHIP, EALIGN, EOFFSETS, ENOTUNED, ECAPTURE = 0, -1, -2, -3, -4, -5, -6, -7
 PLAIN, FAST, RIGOROUS, WIDE, KAHAN, FAST_ROUNDED, RIGOROUS_ROUNDED, MIXED = 0, 1, 2, 3, 4, 5, 6, 7
 FLAG_ERROR, FLAG_LENGTH, FLAG_NONFINITE = 1, 2, 4
 
@@ -34,6 +34,7 @@ _LP = ctypes.POINTER(Launch)
 
 SIGNATURES = {
     "twofold_default_launch": (_int, [_int, _int, _int, _int, _i64, _i64, _LP]),
+    "twofold_tuned_launch": (_int, [_int, _int, _int, _int, _i64, _i64, _LP]),
     "twofold_workspace_bytes_single": (_sz, [_int, _int, _int, _i64, _LP]),
     "twofold_workspace_bytes_seg": (_sz, [_int, _int, _int, _i64, _i64, _LP]),
     "twofold_sum_f32": (_int, [_vp, _i64, _int, _LP, _vp, _vp, _sz, _vp]),

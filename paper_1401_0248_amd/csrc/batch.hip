@@ -29,49 +29,50 @@ struct BatchArgs {
   BatchEntry e[kMaxBatch];
 };
 
-template <typename T, bool DOT, bool YV, int U>
+template <typename T, bool DOT, bool YV, int U, int BMAX>
 __device__ __forceinline__ void batch_item(const BatchEntry& b, int mode, double* part) {
   const T* x = static_cast<const T*>(b.x);
   const T* y = static_cast<const T*>(b.y);
+  constexpr bool AH = rounds_ahead<BMAX, DOT, U>();
   switch (mode) {
-    case kPlain: single_block<T, T, kPlain, DOT, YV, U>(x, y, b.n, part, b.out, 0); break;
-    case kFast: single_block<T, T, kFast, DOT, YV, U>(x, y, b.n, part, b.out, 0); break;
-    case kRigorous: single_block<T, T, kRigorous, DOT, YV, U>(x, y, b.n, part, b.out, 0); break;
-    case kKahan: single_block<T, T, kKahan, DOT, YV, U>(x, y, b.n, part, b.out, 0); break;
+    case kPlain: single_block<T, T, kPlain, DOT, YV, U, AH>(x, y, b.n, part, b.out, 0); break;
+    case kFast: single_block<T, T, kFast, DOT, YV, U, AH>(x, y, b.n, part, b.out, 0); break;
+    case kRigorous: single_block<T, T, kRigorous, DOT, YV, U, AH>(x, y, b.n, part, b.out, 0); break;
+    case kKahan: single_block<T, T, kKahan, DOT, YV, U, AH>(x, y, b.n, part, b.out, 0); break;
     case kFastRounded:
-      if constexpr (DOT) single_block<T, T, kFastRounded, DOT, YV, U>(x, y, b.n, part, b.out, 0);
+      if constexpr (DOT) single_block<T, T, kFastRounded, DOT, YV, U, AH>(x, y, b.n, part, b.out, 0);
       break;
     default:
-      if constexpr (DOT) single_block<T, T, kRigorousRounded, DOT, YV, U>(x, y, b.n, part, b.out, 0);
+      if constexpr (DOT) single_block<T, T, kRigorousRounded, DOT, YV, U, AH>(x, y, b.n, part, b.out, 0);
       break;
   }
 }
 
-template <typename T, int U>
+template <typename T, int U, int BMAX>
 __device__ __forceinline__ void batch_by_op(const BatchEntry& b, int64_t kind, double* part) {
   const int mode = static_cast<int>(kind >> 3);
   if (kind & 2) {
     if (kind & 4)
-      batch_item<T, true, true, U>(b, mode, part);
+      batch_item<T, true, true, U, BMAX>(b, mode, part);
     else
-      batch_item<T, true, false, U>(b, mode, part);
+      batch_item<T, true, false, U, BMAX>(b, mode, part);
   } else {
-    batch_item<T, false, true, U>(b, mode, part);
+    batch_item<T, false, true, U, BMAX>(b, mode, part);
   }
 }
 
 // Pass 1: sets of gridDim.x blocks as in the multi-vector kernel; item v's
 // block pairs at part[v * gridDim.x ...].
-template <int U>
-__global__ void __launch_bounds__(1024)
+template <int U, int BMAX>
+__global__ void __launch_bounds__(BMAX)
 batch_kernel(const BatchArgs args, int count, double* __restrict__ part) {
   for (int v = blockIdx.y; v < count; v += gridDim.y) {
     const BatchEntry& b = args.e[v];
     double* p = part + 2 * static_cast<int64_t>(v) * gridDim.x;
     if (b.kind & 1)
-      batch_by_op<double, U>(b, b.kind, p);
+      batch_by_op<double, U, BMAX>(b, b.kind, p);
     else
-      batch_by_op<float, U>(b, b.kind, p);
+      batch_by_op<float, U, BMAX>(b, b.kind, p);
     __syncthreads();  // the block combine's LDS is reused for the next item
   }
 }
@@ -80,22 +81,23 @@ batch_kernel(const BatchArgs args, int count, double* __restrict__ part) {
 // data, double-word for binary64 data) and the mixed form (binary32 data).
 // A kernel of their own, so that batches of same-type forms keep the leaner
 // kernel above.
-template <bool DOT, bool YV, int U>
+template <bool DOT, bool YV, int U, int BMAX>
 __device__ __forceinline__ void batch_item_wide(const BatchEntry& b, int64_t kind, double* part) {
+  constexpr bool AH = rounds_ahead<BMAX, DOT, U>();
   if (kind & 1) {
-    single_block<double, double, kDoubleDouble, DOT, YV, U>(
+    single_block<double, double, kDoubleDouble, DOT, YV, U, AH>(
         static_cast<const double*>(b.x), static_cast<const double*>(b.y), b.n, part, b.out, 0);
   } else if ((kind >> 3) == kMixed) {
-    single_block<float, double, kMixed, DOT, YV, U>(
+    single_block<float, double, kMixed, DOT, YV, U, AH>(
         static_cast<const float*>(b.x), static_cast<const float*>(b.y), b.n, part, b.out, 0);
   } else {
-    single_block<float, double, kWide, DOT, YV, U>(
+    single_block<float, double, kWide, DOT, YV, U, AH>(
         static_cast<const float*>(b.x), static_cast<const float*>(b.y), b.n, part, b.out, 0);
   }
 }
 
-template <int U>
-__global__ void __launch_bounds__(1024)
+template <int U, int BMAX>
+__global__ void __launch_bounds__(BMAX)
 batch_kernel_wide(const BatchArgs args, int count, double* __restrict__ part) {
   for (int v = blockIdx.y; v < count; v += gridDim.y) {
     const BatchEntry& b = args.e[v];
@@ -104,16 +106,16 @@ batch_kernel_wide(const BatchArgs args, int count, double* __restrict__ part) {
     if (mode == kWide || mode == kMixed) {
       if (b.kind & 2) {
         if (b.kind & 4)
-          batch_item_wide<true, true, U>(b, b.kind, p);
+          batch_item_wide<true, true, U, BMAX>(b, b.kind, p);
         else
-          batch_item_wide<true, false, U>(b, b.kind, p);
+          batch_item_wide<true, false, U, BMAX>(b, b.kind, p);
       } else {
-        batch_item_wide<false, true, U>(b, b.kind, p);
+        batch_item_wide<false, true, U, BMAX>(b, b.kind, p);
       }
     } else if (b.kind & 1) {
-      batch_by_op<double, U>(b, b.kind, p);
+      batch_by_op<double, U, BMAX>(b, b.kind, p);
     } else {
-      batch_by_op<float, U>(b, b.kind, p);
+      batch_by_op<float, U, BMAX>(b, b.kind, p);
     }
     __syncthreads();
   }
@@ -179,7 +181,7 @@ int resolve_batch(const twofold_batch_item_t* items, int64_t count,
   for (int64_t v = 0; v < count; v++) {
     const twofold_batch_item_t& it = items[v];
     if (!valid_dtype(it.dtype) || !valid_count(it.n) || (it.is_dot != 0 && it.is_dot != 1) ||
-        !batch_mode_ok(it.dtype, it.is_dot != 0, it.mode))
+        !batch_mode_ok(it.dtype, it.is_dot != 0, it.mode) || it.reserved != 0)
       return TWOFOLD_EINVAL;
     if (item_bytes(it) > best) {
       best = item_bytes(it);
@@ -190,27 +192,24 @@ int resolve_batch(const twofold_batch_item_t* items, int64_t count,
   if (count == 0) return TWOFOLD_OK;
   const twofold_batch_item_t& m = items[bi];
   const int rc = resolve_single(m.dtype, m.is_dot != 0, m.mode, m.n, launch, lc);
-  // the batch kernel holds every form's code; above four vectors a round it
-  // spills, so a default launch takes at most four
-  if (!rc && !launch && lc->unroll > 4) lc->unroll = 4;
+  // the batch kernel holds every form's code; its instance for blocks of
+  // up to 1024 threads spills above four vectors a round, so a default
+  // launch of such blocks takes at most four
+  if (!rc && !launch && lc->unroll > 4 && lc->block_threads > kSmallBlock) lc->unroll = 4;
   return rc;
 }
 
-template <int U>
-int launch_batch_u(const BatchArgs& a, int count, int sets, bool wide, const twofold_launch_t& lc,
-                   double* part, hipStream_t st) {
+int launch_batch(const BatchArgs& a, int count, int sets, bool wide, const twofold_launch_t& lc,
+                 double* part, hipStream_t st) {
   const dim3 grid(lc.grid_blocks, unsigned(sets)), block(lc.block_threads);
-  if (wide)
-    batch_kernel_wide<U><<<grid, block, 0, st>>>(a, count, part);
-  else
-    batch_kernel<U><<<grid, block, 0, st>>>(a, count, part);
-  if (launch_status()) return TWOFOLD_EHIP;
-  if (lc.grid_blocks > 1) {
-    batch_pass2_kernel<<<dim3(unsigned(count)), dim3(kPass2Lanes), 0, st>>>(a, part,
-                                                                            lc.grid_blocks);
-    return launch_status();
-  }
-  return TWOFOLD_OK;
+  const int rc = by_shape(lc, [&](auto u, auto bmax) {
+    constexpr int U = decltype(u)::value, BMAX = decltype(bmax)::value;
+    return wide ? launch_kernel(batch_kernel_wide<U, BMAX>, grid, block, st, a, count, part)
+                : launch_kernel(batch_kernel<U, BMAX>, grid, block, st, a, count, part);
+  });
+  if (rc || lc.grid_blocks == 1) return rc;
+  return launch_kernel(batch_pass2_kernel, dim3(unsigned(count)), dim3(kPass2Lanes), st, a, part,
+                       lc.grid_blocks);
 }
 
 }  // namespace
@@ -226,8 +225,13 @@ size_t twofold_workspace_bytes_batch(const twofold_batch_item_t* items, int64_t 
   return multi_ws_bytes(lc, count);
 }
 
-int twofold_batch(const twofold_batch_item_t* items, int64_t count,
-                  const twofold_launch_t* launch, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// twofold_batch: the block pairs in ws.
+int batch_common(const twofold_batch_item_t* items, int64_t count, const twofold_launch_t* launch,
+                 void* ws, size_t ws_bytes, void* stream) {
   twofold_launch_t lc;
   int64_t max_bytes = 0;
   const int rc = resolve_batch(items, count, launch, &lc, &max_bytes);
@@ -259,13 +263,16 @@ int twofold_batch(const twofold_batch_item_t* items, int64_t count,
   const int sets = max_bytes <= kBatchSideBytes ? int(count) : 1;
   double* part = static_cast<double*>(ws);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int c = int(count);
-  switch (lc.unroll) {
-    case 1: return launch_batch_u<1>(a, c, sets, wide, lc, part, st);
-    case 2: return launch_batch_u<2>(a, c, sets, wide, lc, part, st);
-    case 4: return launch_batch_u<4>(a, c, sets, wide, lc, part, st);
-    default: return launch_batch_u<8>(a, c, sets, wide, lc, part, st);
-  }
+  return launch_batch(a, int(count), sets, wide, lc, part, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int twofold_batch(const twofold_batch_item_t* items, int64_t count,
+                  const twofold_launch_t* launch, void* ws, size_t ws_bytes, void* stream) {
+  return batch_common(items, count, launch, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -33,11 +33,15 @@ enum Mode : int {
   kFastRounded = 5,
   kRigorousRounded = 6,
   kMixed = 7,
-  kDoubleDouble = 8
+  kDoubleDouble = 8,
+  // Instrument only (the read probe): the "step" ORs the bits of the loaded
+  // binary32 words into s, so the reductions' own load loop runs with no
+  // arithmetic to wait for.
+  kProbeOr = 9
 };
 
-// Modes whose pairs carry an error (all but plain and wide).
-constexpr bool has_error(int m) { return m != kPlain && m != kWide; }
+// Modes whose pairs carry an error (all but plain, wide and the probe).
+constexpr bool has_error(int m) { return m != kPlain && m != kWide && m != kProbeOr; }
 
 // The combine used once block pairs are binary64 (step 7): a mixed pair's
 // value is then a binary64 sum, combined like a rigorous pair.
@@ -89,7 +93,12 @@ __device__ __forceinline__ void dw_add_dw(double& h, double& l, double yh, doubl
 // to binary64 and summed plainly).
 template <int M, bool DOT, typename T, typename A>
 __device__ __forceinline__ void step(A& s, A& e, T xv, T yv) {
-  if constexpr (M == kWide) {
+  if constexpr (M == kProbeOr) {
+    static_assert(sizeof(T) == 4 && sizeof(A) == 4, "probe: binary32 words");
+    uint32_t b = __float_as_uint(s) | __float_as_uint(xv);
+    if constexpr (DOT) b |= __float_as_uint(yv);
+    s = __uint_as_float(b);
+  } else if constexpr (M == kWide) {
     A item = DOT ? static_cast<A>(xv) * static_cast<A>(yv) : static_cast<A>(xv);
     s = s + item;
   } else if constexpr (M == kDoubleDouble) {
@@ -167,7 +176,10 @@ __device__ __forceinline__ void step(A& s, A& e, T xv, T yv) {
 // pairs carry no error; double-word pairs are added with AccurateDWPlusDW.
 template <int M, typename A>
 __device__ __forceinline__ void combine(A& s1, A& e1, A s2, A e2) {
-  if constexpr (!has_error(M)) {
+  if constexpr (M == kProbeOr) {
+    s1 = __uint_as_float(__float_as_uint(s1) | __float_as_uint(s2));
+    e1 = A(0);
+  } else if constexpr (!has_error(M)) {
     s1 = s1 + s2;
     e1 = A(0);
   } else if constexpr (M == kDoubleDouble) {

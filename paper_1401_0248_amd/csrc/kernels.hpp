@@ -16,6 +16,32 @@ namespace twofold {
 
 constexpr int kPass2Lanes = 256;  // lanes of the binary64 grid combine
 
+// Register budget. A kernel that may run blocks of 1024 threads must fit 16
+// waves on a CU, four on each SIMD, and so gets at most 128 VGPRs a lane;
+// one that runs blocks of at most 512 threads needs two waves a SIMD and
+// may use 256. Each streaming kernel is built in both sizes (template
+// parameter BMAX, its __launch_bounds__) and the host picks the instance
+// from the launch's block size.
+//
+// Whether a lane keeps a second round of loads in flight while it works on
+// the current one depends on what fits: two rounds of R = U*(1 + dot)
+// 16-byte vectors take 8R VGPRs. Under the narrow budget that leaves room
+// for R <= 4; under the wide one for R <= 8, i.e. every width but eight-
+// vector dots, whose 128 VGPRs of buffers fit beside the rest of the
+// single-vector kernel (216-253 VGPRs, no spill) but not beside the larger
+// state of the multi-vector, batch and segmented kernels.
+constexpr int kSmallBlock = 512;
+
+template <int BMAX, bool DOT, int U>
+constexpr bool rounds_ahead() {
+  return U * (DOT ? 2 : 1) <= (BMAX <= kSmallBlock ? 8 : 4);
+}
+
+template <int BMAX, bool DOT, int U>
+constexpr bool rounds_ahead_single() {
+  return BMAX <= kSmallBlock || rounds_ahead<BMAX, DOT, U>();
+}
+
 template <typename T> struct vec16;
 template <> struct vec16<float> { using type = float4; };
 template <> struct vec16<double> { using type = double2; };
@@ -90,22 +116,19 @@ __device__ __forceinline__ int64_t head_count(const T* p, int64_t len) {
 // Steps 1-4 of the documented order for one lane g of L lanes over the
 // range [x, x + len): head, rounds of U vectors, tail, chain merge.
 //
-// The head and tail elements are requested first. With at most four
-// vectors per round (U = 1, 2, 4 for a sum, U = 1, 2 for a dot) the loads
-// also run one round ahead of the arithmetic: round 0 is requested with the
-// head and tail, and while the steps of round q run, the loads of round
-// q + 1 (or of the last, partial round) are in flight. Wider rounds already
-// keep enough bytes in flight per lane and would not fit two rounds in the
-// 128 registers of a 1024-thread block, so they load each round when it
-// starts. Either way the steps are applied in the documented order (head,
-// rounds in order, partial round, tail), so the result does not depend on
-// when the data arrived.
-template <typename T, typename A, int M, bool DOT, bool YV, int U>
+// The head and tail elements are requested first. With AHEAD (see
+// rounds_ahead) the loads also run one round ahead of the arithmetic: round
+// 0 is requested with the head and tail, and while the steps of round q
+// run, the loads of round q + 1 (or of the last, partial round) are in
+// flight. Without it each round is loaded when it starts. Either way the
+// steps are applied in the documented order (head, rounds in order, partial
+// round, tail), so the result does not depend on when the data arrived.
+template <typename T, typename A, int M, bool DOT, bool YV, int U, bool AHEAD>
 __device__ __forceinline__ void lane_reduce(const T* __restrict__ x, const T* __restrict__ y,
                                             int64_t len, int64_t head, int64_t L, int64_t g,
                                             A& s_out, A& e_out) {
   constexpr int W = 16 / static_cast<int>(sizeof(T));
-  constexpr bool kAhead = U * (DOT ? 2 : 1) <= 4;
+  constexpr bool kAhead = AHEAD;
   using V = typename vec16<T>::type;
   A cs[W], ce[W];
 #pragma unroll
@@ -281,7 +304,7 @@ __device__ __forceinline__ void block_store(A s, A e, double* __restrict__ part,
 
 // Steps 1-6 for block blockIdx.x of a grid of gridDim.x blocks over one
 // vector.
-template <typename T, typename A, int M, bool DOT, bool YV, int U>
+template <typename T, typename A, int M, bool DOT, bool YV, int U, bool AHEAD>
 __device__ __forceinline__ void single_block(const T* __restrict__ x, const T* __restrict__ y,
                                              int64_t n, double* __restrict__ part,
                                              void* __restrict__ out, int64_t idx) {
@@ -289,21 +312,15 @@ __device__ __forceinline__ void single_block(const T* __restrict__ x, const T* _
   const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t head = head_count(x, n);
   A s, e;
-  lane_reduce<T, A, M, DOT, YV, U>(x, y, n, head, L, g, s, e);
+  lane_reduce<T, A, M, DOT, YV, U, AHEAD>(x, y, n, head, L, g, s, e);
   block_store<T, A, M>(s, e, part, out, idx);
 }
 
-template <typename T, typename A, int M, bool DOT, bool YV, int U>
-__global__ void __launch_bounds__(1024)
+template <typename T, typename A, int M, bool DOT, bool YV, int U, int BMAX>
+__global__ void __launch_bounds__(BMAX)
 single_kernel(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
               double* __restrict__ part, void* __restrict__ out) {
-  single_block<T, A, M, DOT, YV, U>(x, y, n, part, out, 0);
-}
-
-// Whether a lane keeps two rounds in registers (loads one round ahead).
-template <typename T, bool DOT, int U>
-constexpr bool rounds_ahead() {
-  return U * (DOT ? 2 : 1) <= 4;
+  single_block<T, A, M, DOT, YV, U, rounds_ahead_single<BMAX, DOT, U>()>(x, y, n, part, out, 0);
 }
 
 // ---- several vectors in one launch ------------------------------------------
@@ -324,12 +341,12 @@ struct MultiArgs {
   int64_t n[kMaxMulti];
 };
 
-template <typename T, typename A, int M, bool DOT, bool YV, int U>
-__global__ void __launch_bounds__(1024)
+template <typename T, typename A, int M, bool DOT, bool YV, int U, int BMAX>
+__global__ void __launch_bounds__(BMAX)
 multi_kernel(const MultiArgs<T> args, int count, double* __restrict__ part,
              void* __restrict__ out) {
   for (int v = blockIdx.y; v < count; v += gridDim.y) {
-    single_block<T, A, M, DOT, YV, U>(args.x[v], args.y[v], args.n[v],
+    single_block<T, A, M, DOT, YV, U, rounds_ahead<BMAX, DOT, U>()>(args.x[v], args.y[v], args.n[v],
                                       part + 2 * static_cast<int64_t>(v) * gridDim.x, out, v);
     __syncthreads();  // the block combine's LDS is reused for the next vector
   }
@@ -622,8 +639,8 @@ __device__ __forceinline__ int64_t seg_cost_bound(int64_t w, int64_t C, int64_t 
 // interleaved binary searches over the segments' costs. A one-tile segment
 // is finalized here; the pair of a tile of a longer segment goes to
 // slots[tile].
-template <typename T, typename A, int M, bool DOT, bool YV, int U>
-__global__ void __launch_bounds__(1024)
+template <typename T, typename A, int M, bool DOT, bool YV, int U, int BMAX>
+__global__ void __launch_bounds__(BMAX)
 seg_kernel(const T* __restrict__ x, const T* __restrict__ y, const int64_t* __restrict__ off,
            int64_t nseg, const int64_t* __restrict__ tbase, const int64_t* __restrict__ wtab,
            int64_t TS, const uint32_t* __restrict__ status, double* __restrict__ slots,
@@ -668,49 +685,73 @@ seg_kernel(const T* __restrict__ x, const T* __restrict__ y, const int64_t* __re
   if (t0 >= t1) return;
   SegWalk wk{off, tbase, nseg, TS, sg};
   wk.start(t0);
-  if constexpr (rounds_ahead<T, DOT, U>()) {
+  if constexpr (rounds_ahead<BMAX, DOT, U>()) {
     seg_tiles_ahead<T, A, M, DOT, YV, U>(x, y, wk, t0, t1, lane, slots, out);
   } else {
+    // Tile by tile. Under the wide register budget (eight-vector dots: the
+    // cross-tile walk would need a third round buffer) the binary32 forms
+    // still keep their loads a round ahead inside each tile; the forms with
+    // binary64 chains would spill doing so (12-36 bytes a lane), so they
+    // load each round when it starts.
+    constexpr bool kInTile = BMAX <= kSmallBlock && sizeof(A) == 4;
     for (int64_t t = t0; t < t1; t++) {
       wk.to(t);
       const int64_t a = wk.begin(t), b = wk.end(t);
       const T* xa = x + a;
       const T* ya = DOT ? y + a : nullptr;
       A s, e;
-      lane_reduce<T, A, M, DOT, YV, U>(xa, ya, b - a, head_count(xa, b - a), 64, lane, s, e);
+      lane_reduce<T, A, M, DOT, YV, U, kInTile>(xa, ya, b - a, head_count(xa, b - a), 64, lane, s,
+                                                e);
       tile_store<T, A, M>(s, e, lane, t, wk.sg, wk.tend - wk.tb, slots, out);
     }
   }
 }
 
-// Pass 2: one wave per segment. Empty segments get (+0, +0); segments of
-// two or more tiles combine their tile pairs in binary64 (lane l takes
-// tiles l, l + 64, ... in tile order), then the wave combine and step 8.
-// With invalid offsets (device-offset path) every output is NaN.
+// Pass 2: one wave per segment, the waves of the grid striding over the
+// segments (so the grid stays small for any segment count). Empty segments
+// get (+0, +0); segments of two or more tiles combine their tile pairs in
+// binary64 (lane l takes tiles l, l + 64, ... in tile order), then the wave
+// combine and step 8. With invalid offsets (device-offset path) every
+// output is NaN.
+constexpr int kSegPass2Threads = 256;
+constexpr int64_t kSegPass2MaxBlocks = 8192;
+
+// Blocks of a pass-2 launch over nseg segments: one wave per segment up to
+// kSegPass2MaxBlocks blocks, then the waves stride.
+inline int64_t seg_pass2_blocks(int64_t nseg) {
+  const int64_t wpb = kSegPass2Threads / 64;
+  const int64_t b = (nseg + wpb - 1) / wpb;
+  return b < 1 ? 1 : (b > kSegPass2MaxBlocks ? kSegPass2MaxBlocks : b);
+}
+
 template <typename T, int M>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kSegPass2Threads)
 seg_pass2_kernel(const int64_t* __restrict__ tbase, int64_t nseg,
                  const uint32_t* __restrict__ status, const double* __restrict__ slots,
                  void* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t sg = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (sg >= nseg) return;
-  if (status && *status != 0) {
-    if (lane == 0) store_nan_pair(out, sg, out_is_f64<T, M>());
-    return;
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * wpb;
+  const bool bad = status && *status != 0;
+  for (int64_t sg = static_cast<int64_t>(blockIdx.x) * wpb + (threadIdx.x >> 6); sg < nseg;
+       sg += nw) {
+    if (bad) {
+      if (lane == 0) store_nan_pair(out, sg, out_is_f64<T, M>());
+      continue;
+    }
+    const int64_t tb = tbase[sg];
+    const int64_t ntl = tbase[sg + 1] - tb;
+    if (ntl == 1) continue;
+    if (ntl == 0) {
+      if (lane == 0) finalize_store<T, M>(out, sg, 0.0, 0.0);
+      continue;
+    }
+    constexpr int P = pass2_mode(M);
+    double qs = 0.0, qe = 0.0;
+    combine_strided<P>(reinterpret_cast<const double2*>(slots) + tb, ntl, lane, 64, qs, qe);
+    wave_combine<P>(qs, qe);
+    if (lane == 0) finalize_store<T, M>(out, sg, qs, qe);
   }
-  const int64_t tb = tbase[sg];
-  const int64_t ntl = tbase[sg + 1] - tb;
-  if (ntl == 1) return;
-  if (ntl == 0) {
-    if (lane == 0) finalize_store<T, M>(out, sg, 0.0, 0.0);
-    return;
-  }
-  constexpr int P = pass2_mode(M);
-  double qs = 0.0, qe = 0.0;
-  combine_strided<P>(reinterpret_cast<const double2*>(slots) + tb, ntl, lane, 64, qs, qe);
-  wave_combine<P>(qs, qe);
-  if (lane == 0) finalize_store<T, M>(out, sg, qs, qe);
 }
 
 }  // namespace twofold

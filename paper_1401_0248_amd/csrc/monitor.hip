@@ -61,19 +61,18 @@ int twofold_monitor(int dtype, const void* pairs, int64_t count, const int64_t* 
     return TWOFOLD_EALIGN;
   hipStream_t st = static_cast<hipStream_t>(stream);
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(nflagged);
-  zero_count_kernel<<<1, 1, 0, st>>>(cnt);
-  if (launch_status()) return TWOFOLD_EHIP;
-  if (count == 0) return TWOFOLD_OK;
+  const int rc = launch_kernel(zero_count_kernel, dim3(1), dim3(1), st, cnt);
+  if (rc || count == 0) return rc;
   int64_t blocks = (count + 255) / 256;
   if (blocks > 1024) blocks = 1024;
   const int64_t inv_u = dtype == 4 ? (int64_t(1) << 24) : (int64_t(1) << 53);
   if (dtype == 4)
-    monitor_kernel<float><<<dim3(unsigned(blocks)), dim3(256), 0, st>>>(
-        static_cast<const float*>(pairs), count, offsets, n, tau, inv_u, flags, cnt);
-  else
-    monitor_kernel<double><<<dim3(unsigned(blocks)), dim3(256), 0, st>>>(
-        static_cast<const double*>(pairs), count, offsets, n, tau, inv_u, flags, cnt);
-  return launch_status();
+    return launch_kernel(monitor_kernel<float>, dim3(unsigned(blocks)), dim3(256), st,
+                         static_cast<const float*>(pairs), count, offsets, n, tau, inv_u, flags,
+                         cnt);
+  return launch_kernel(monitor_kernel<double>, dim3(unsigned(blocks)), dim3(256), st,
+                       static_cast<const double*>(pairs), count, offsets, n, tau, inv_u, flags,
+                       cnt);
 }
 
 }  // extern "C"

@@ -1,70 +1,43 @@
 // probes.hip: the measuring instruments of the library, gfx950 versions of
 // the paper's read1/read2 memory-only functions (section "Memory reading")
 // and its p-functions that compute without reading memory (section "Purely
-// computing"). They bound the reduction kernels from above: the read probe
-// gives the achievable HBM stream rate, the compute probe the ALU rate of
-// each summation step when no data has to be fetched.
+// computing").
+//
+// The read probe runs the single-vector kernel's own lane loop (lane_reduce:
+// the same 16-byte non-temporal loads in the same lane order, the same
+// loads one round ahead, the same register budget per block size) with the
+// summation step replaced by a bit-OR of the loaded words, so it measures
+// what that loop can stream when no arithmetic has to keep up. The compute
+// probe runs each form's step on register-resident items, with no memory
+// traffic: the ALU rate of each summation step.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
 
-#include "eft.hpp"
+#include "host_common.hpp"
+#include "kernels.hpp"
 #include "twofold.h"
 
 using namespace twofold;
+using namespace twofold::host;
 
 namespace {
 
-// Stream one or two arrays with 16-byte non-temporal loads (the load the
-// reduction kernels use) in the single-vector lane order and fold every
-// loaded bit into one word, so no load is dead code.
-typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ uint4 load_nt16(const uint4* p) {
-  const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
-  return make_uint4(v.x, v.y, v.z, v.w);
-}
-
-template <bool TWO, int U>
-__global__ void __launch_bounds__(1024)
-read_probe_kernel(const uint4* __restrict__ x, const uint4* __restrict__ y, int64_t nvec,
+// One or two arrays of binary32 words (n words each, 16-byte aligned, n a
+// multiple of 4) in the single-vector lane order of the launch; each block
+// writes the OR of every word its lanes loaded to sink[block].
+template <bool TWO, int U, int BMAX>
+__global__ void __launch_bounds__(BMAX)
+read_probe_kernel(const float* __restrict__ x, const float* __restrict__ y, int64_t n,
                   uint64_t* __restrict__ sink) {
   const int64_t L = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  uint32_t acc = 0;
-  const int64_t per_round = int64_t(U) * L;
-  const int64_t full = nvec / per_round;
-  int64_t k0 = g;
-  for (int64_t q = 0; q < full; q++, k0 += per_round) {
-    uint4 a[U], b[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) a[u] = load_nt16(x + k0 + u * L);
-    if constexpr (TWO) {
-#pragma unroll
-      for (int u = 0; u < U; u++) b[u] = load_nt16(y + k0 + u * L);
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      acc |= a[u].x | a[u].y | a[u].z | a[u].w;
-      if constexpr (TWO) acc |= b[u].x | b[u].y | b[u].z | b[u].w;
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < U; u++) {
-    const int64_t k = k0 + u * L;
-    if (k < nvec) {
-      const uint4 a = load_nt16(x + k);
-      acc |= a.x | a.y | a.z | a.w;
-      if constexpr (TWO) {
-        const uint4 b = load_nt16(y + k);
-        acc |= b.x | b.y | b.z | b.w;
-      }
-    }
-  }
-  // One word per block: OR across the block through LDS.
+  float s, e;
+  lane_reduce<float, float, kProbeOr, TWO, true, U, rounds_ahead_single<BMAX, TWO, U>()>(
+      x, y, n, 0, L, g, s, e);
+  wave_combine<kProbeOr>(s, e);
   __shared__ uint32_t sh[16];
-  for (int d = 1; d < 64; d <<= 1) acc |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(acc), d));
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = __float_as_uint(s);
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t r = 0;
@@ -122,9 +95,8 @@ compute_probe_kernel(const T* __restrict__ seed, int64_t iters, double* __restri
 template <typename T, typename A, int M, bool DOT>
 int launch_compute(const void* seed, int64_t iters, const twofold_launch_t& lc, double* sink,
                    hipStream_t st) {
-  compute_probe_kernel<T, A, M, DOT, 4><<<dim3(lc.grid_blocks), dim3(lc.block_threads), 0, st>>>(
-      static_cast<const T*>(seed), iters, sink);
-  return hipGetLastError() == hipSuccess ? TWOFOLD_OK : TWOFOLD_EHIP;
+  return launch_kernel(compute_probe_kernel<T, A, M, DOT, 4>, dim3(lc.grid_blocks),
+                       dim3(lc.block_threads), st, static_cast<const T*>(seed), iters, sink);
 }
 
 template <typename T, bool DOT>
@@ -165,28 +137,22 @@ extern "C" {
 
 int twofold_probe_read(const void* x, const void* y, int64_t nbytes, const twofold_launch_t* launch,
                        uint64_t* sink, void* stream) {
-  if (!x || !sink || nbytes < 0 || nbytes % 16 || !launch_ok(launch)) return TWOFOLD_EINVAL;
+  if (!x || !sink || nbytes < 0 || nbytes % 16 || !launch_ok(launch) ||
+      !valid_unroll(launch->unroll))
+    return TWOFOLD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(x) & 15u) || (y && (reinterpret_cast<uintptr_t>(y) & 15u)) ||
       (reinterpret_cast<uintptr_t>(sink) & 7u))
     return TWOFOLD_EALIGN;
-  const int64_t nvec = nbytes / 16;
+  const int64_t n = nbytes / 4;
   const dim3 grid(launch->grid_blocks), block(launch->block_threads);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const uint4* xv = static_cast<const uint4*>(x);
-  const uint4* yv = static_cast<const uint4*>(y);
-#define TWOFOLD_READ(TWO, UU) read_probe_kernel<TWO, UU><<<grid, block, 0, st>>>(xv, yv, nvec, sink)
-  const int u = launch->unroll;
-  if (y) {
-    if (u == 1) TWOFOLD_READ(true, 1); else if (u == 2) TWOFOLD_READ(true, 2);
-    else if (u == 4) TWOFOLD_READ(true, 4); else if (u == 8) TWOFOLD_READ(true, 8);
-    else return TWOFOLD_EINVAL;
-  } else {
-    if (u == 1) TWOFOLD_READ(false, 1); else if (u == 2) TWOFOLD_READ(false, 2);
-    else if (u == 4) TWOFOLD_READ(false, 4); else if (u == 8) TWOFOLD_READ(false, 8);
-    else return TWOFOLD_EINVAL;
-  }
-#undef TWOFOLD_READ
-  return hipGetLastError() == hipSuccess ? TWOFOLD_OK : TWOFOLD_EHIP;
+  const float* xf = static_cast<const float*>(x);
+  const float* yf = static_cast<const float*>(y);
+  return by_shape(*launch, [&](auto u, auto bmax) {
+    constexpr int U = decltype(u)::value, BMAX = decltype(bmax)::value;
+    return y ? launch_kernel(read_probe_kernel<true, U, BMAX>, grid, block, st, xf, yf, n, sink)
+             : launch_kernel(read_probe_kernel<false, U, BMAX>, grid, block, st, xf, yf, n, sink);
+  });
 }
 
 int twofold_probe_compute(int dtype, int is_dot, int mode, const void* seed, int64_t iters,

@@ -63,21 +63,13 @@ int launch_seg_u(const T* x, const T* y, const int64_t* off, int64_t nseg, const
                  double* slots, void* out, hipStream_t st) {
   const dim3 grid(lc.grid_blocks), block(lc.block_threads);
   const int64_t ts = lc.tile_elems;
-#define TWOFOLD_SEG(UU)                                                                       \
-  seg_kernel<T, A, M, DOT, YV, UU><<<grid, block, 0, st>>>(x, y, off, nseg, tbase, wtab, ts, \
-                                                           status, slots, out)
-  switch (lc.unroll) {
-    case 1: TWOFOLD_SEG(1); break;
-    case 2: TWOFOLD_SEG(2); break;
-    case 4: TWOFOLD_SEG(4); break;
-    default: TWOFOLD_SEG(8); break;
-  }
-#undef TWOFOLD_SEG
-  if (launch_status()) return TWOFOLD_EHIP;
-  const int64_t blocks2 = (nseg + 3) / 4;  // one wave per segment, 4 waves per block
-  seg_pass2_kernel<T, M><<<dim3(unsigned(blocks2)), dim3(256), 0, st>>>(tbase, nseg, status, slots,
-                                                                        out);
-  return launch_status();
+  const int rc = by_shape(lc, [&](auto u, auto bmax) {
+    return launch_kernel(seg_kernel<T, A, M, DOT, YV, decltype(u)::value, decltype(bmax)::value>,
+                         grid, block, st, x, y, off, nseg, tbase, wtab, ts, status, slots, out);
+  });
+  if (rc) return rc;
+  return launch_kernel(seg_pass2_kernel<T, M>, dim3(unsigned(seg_pass2_blocks(nseg))),
+                       dim3(kSegPass2Threads), st, tbase, nseg, status, slots, out);
 }
 
 template <typename T, typename A, int M, bool DOT>
@@ -145,8 +137,9 @@ int seg_entry(const T* x, const T* y, int64_t n_total, const int64_t* off, int64
   int64_t* tbase = reinterpret_cast<int64_t*>(base + L.tbase_off);
   double* slots = reinterpret_cast<double*>(base + L.slots_off);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  seg_tiles_kernel<<<1, 1024, 0, st>>>(off, nseg, n_total, lc.tile_elems, tbase, status);
-  if (launch_status()) return TWOFOLD_EHIP;
+  const int rc2 = launch_kernel(seg_tiles_kernel, dim3(1), dim3(1024), st, off, nseg, n_total,
+                                lc.tile_elems, tbase, status);
+  if (rc2) return rc2;
   return seg_by_mode<T, DOT>(mode, x, y, off, nseg, tbase, nullptr, status, lc, slots, out, st);
 }
 
@@ -173,6 +166,33 @@ void build_wave_table(const int64_t* off, const int64_t* tb, int64_t nseg, int64
     wt[2 * w] = t;
     wt[2 * w + 1] = sg;
   }
+}
+
+// Stream capture, as far as a call that is given no stream can see it. The
+// legacy default stream reports a capture under way on any blocking
+// stream (hipErrorStreamCaptureImplicit); a global-mode capture on a
+// non-blocking stream shows up only as the allocator's refusal, one of the
+// capture errors 900-908 of hip_runtime_api.h.
+//
+// The query and a refused allocation leave their error in the thread's HIP
+// error state, where a later, unrelated launch check (torch's, say) would
+// find it. Both are therefore cleared again, unless an error was already
+// pending before plan creation made any HIP call (that one stays).
+bool capture_under_way(bool state_was_clean) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(nullptr, &cs);
+  if (e != hipSuccess && state_was_clean) (void)hipGetLastError();
+  return e == hipErrorStreamCaptureImplicit ||
+         (e == hipSuccess && cs != hipStreamCaptureStatusNone);
+}
+
+int refuse_capture(bool state_was_clean) {
+  if (state_was_clean) (void)hipGetLastError();
+  return TWOFOLD_ECAPTURE;
+}
+
+bool is_capture_error(hipError_t e) {
+  return e >= hipErrorStreamCaptureUnsupported && e <= hipErrorStreamCaptureWrongThread;
 }
 
 }  // namespace
@@ -286,6 +306,11 @@ int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype
     acc += (len + lc.tile_elems - 1) / lc.tile_elems;
   }
   tb[nseg] = acc;
+  const bool state_was_clean = hipPeekAtLastError() == hipSuccess;
+  if (capture_under_way(state_was_clean)) {
+    free(tb);
+    return refuse_capture(state_was_clean);
+  }
   twofold_seg_plan* p = static_cast<twofold_seg_plan*>(calloc(1, sizeof(twofold_seg_plan)));
   if (!p) {
     free(tb);
@@ -310,13 +335,19 @@ int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype
     if (ok) build_wave_table(offsets_host, tb, nseg, lc.tile_elems, 64 * (16 / dtype) * lc.unroll,
                              nw, wt);
   }
-  ok = ok && hipMalloc(reinterpret_cast<void**>(&p->d_off), bytes) == hipSuccess &&
-       hipMalloc(reinterpret_cast<void**>(&p->d_tbase), bytes) == hipSuccess &&
-       hipMemcpy(p->d_off, offsets_host, bytes, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(p->d_tbase, tb, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  // the first failing HIP call's error, if any
+  hipError_t he = hipSuccess;
+  auto run = [&](hipError_t e) {
+    if (he == hipSuccess) he = e;
+    return e == hipSuccess;
+  };
+  ok = ok && run(hipMalloc(reinterpret_cast<void**>(&p->d_off), bytes)) &&
+       run(hipMalloc(reinterpret_cast<void**>(&p->d_tbase), bytes)) &&
+       run(hipMemcpy(p->d_off, offsets_host, bytes, hipMemcpyHostToDevice)) &&
+       run(hipMemcpy(p->d_tbase, tb, bytes, hipMemcpyHostToDevice));
   if (ok && wt)
-    ok = hipMalloc(reinterpret_cast<void**>(&p->d_wtab), wbytes) == hipSuccess &&
-         hipMemcpy(p->d_wtab, wt, wbytes, hipMemcpyHostToDevice) == hipSuccess;
+    ok = run(hipMalloc(reinterpret_cast<void**>(&p->d_wtab), wbytes)) &&
+         run(hipMemcpy(p->d_wtab, wt, wbytes, hipMemcpyHostToDevice));
   free(tb);
   free(wt);
   if (!ok) {
@@ -324,7 +355,8 @@ int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype
     if (p->d_tbase) (void)hipFree(p->d_tbase);
     if (p->d_wtab) (void)hipFree(p->d_wtab);
     free(p);
-    return TWOFOLD_EHIP;
+    if (he == hipSuccess) return TWOFOLD_EINVAL;  // host allocation failed
+    return is_capture_error(he) ? refuse_capture(state_was_clean) : TWOFOLD_EHIP;
   }
   *plan = p;
   return TWOFOLD_OK;

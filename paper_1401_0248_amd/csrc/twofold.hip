@@ -21,18 +21,13 @@ template <typename T, typename A, int M, bool DOT, bool YV>
 int launch_single_u(const T* x, const T* y, int64_t n, const twofold_launch_t& lc, double* part,
                     void* out, hipStream_t st) {
   const dim3 grid(lc.grid_blocks), block(lc.block_threads);
-  switch (lc.unroll) {
-    case 1: single_kernel<T, A, M, DOT, YV, 1><<<grid, block, 0, st>>>(x, y, n, part, out); break;
-    case 2: single_kernel<T, A, M, DOT, YV, 2><<<grid, block, 0, st>>>(x, y, n, part, out); break;
-    case 4: single_kernel<T, A, M, DOT, YV, 4><<<grid, block, 0, st>>>(x, y, n, part, out); break;
-    default: single_kernel<T, A, M, DOT, YV, 8><<<grid, block, 0, st>>>(x, y, n, part, out); break;
-  }
-  if (launch_status()) return TWOFOLD_EHIP;
-  if (lc.grid_blocks > 1) {
-    single_pass2_kernel<T, M><<<dim3(1), dim3(kPass2Lanes), 0, st>>>(part, lc.grid_blocks, out);
-    return launch_status();
-  }
-  return TWOFOLD_OK;
+  const int rc = by_shape(lc, [&](auto u, auto bmax) {
+    return launch_kernel(single_kernel<T, A, M, DOT, YV, decltype(u)::value, decltype(bmax)::value>,
+                         grid, block, st, x, y, n, part, out);
+  });
+  if (rc || lc.grid_blocks == 1) return rc;
+  return launch_kernel(single_pass2_kernel<T, M>, dim3(1), dim3(kPass2Lanes), st, part,
+                       lc.grid_blocks, out);
 }
 
 template <typename T, typename A, int M, bool DOT>
@@ -95,19 +90,13 @@ int launch_multi_u(const MultiArgs<T>& a, int64_t count, int sets, const twofold
                    double* part, void* out, hipStream_t st) {
   const dim3 grid(lc.grid_blocks, unsigned(sets)), block(lc.block_threads);
   const int c = int(count);
-  switch (lc.unroll) {
-    case 1: multi_kernel<T, A, M, DOT, YV, 1><<<grid, block, 0, st>>>(a, c, part, out); break;
-    case 2: multi_kernel<T, A, M, DOT, YV, 2><<<grid, block, 0, st>>>(a, c, part, out); break;
-    case 4: multi_kernel<T, A, M, DOT, YV, 4><<<grid, block, 0, st>>>(a, c, part, out); break;
-    default: multi_kernel<T, A, M, DOT, YV, 8><<<grid, block, 0, st>>>(a, c, part, out); break;
-  }
-  if (launch_status()) return TWOFOLD_EHIP;
-  if (lc.grid_blocks > 1) {
-    single_pass2_kernel<T, M><<<dim3(unsigned(count)), dim3(kPass2Lanes), 0, st>>>(
-        part, lc.grid_blocks, out);
-    return launch_status();
-  }
-  return TWOFOLD_OK;
+  const int rc = by_shape(lc, [&](auto u, auto bmax) {
+    return launch_kernel(multi_kernel<T, A, M, DOT, YV, decltype(u)::value, decltype(bmax)::value>,
+                         grid, block, st, a, c, part, out);
+  });
+  if (rc || lc.grid_blocks == 1) return rc;
+  return launch_kernel(single_pass2_kernel<T, M>, dim3(unsigned(count)), dim3(kPass2Lanes), st,
+                       part, lc.grid_blocks, out);
 }
 
 template <typename T, typename A, int M, bool DOT>
@@ -218,6 +207,14 @@ int twofold_default_launch(int kind, int dtype, int is_dot, int mode, int64_t n,
   if (!mode_ok(dtype, is_dot != 0, mode)) return TWOFOLD_EINVAL;
   if (kind == 0) return resolve_single(dtype, is_dot != 0, mode, n, nullptr, out);
   return resolve_seg(dtype, is_dot != 0, mode, n, nullptr, out);
+}
+
+int twofold_tuned_launch(int kind, int dtype, int is_dot, int mode, int64_t n, int64_t nseg,
+                         twofold_launch_t* out) {
+  const int rc = twofold_default_launch(kind, dtype, is_dot, mode, n, nseg, out);
+  if (rc) return rc;
+  twofold_launch_t row;
+  return lookup_rows(kind, dtype, is_dot != 0, mode, n, &row) ? TWOFOLD_OK : TWOFOLD_ENOTUNED;
 }
 
 size_t twofold_workspace_bytes_single(int dtype, int is_dot, int mode, int64_t n,
@@ -355,6 +352,8 @@ const char* twofold_strerror(int status) {
     case TWOFOLD_EHIP: return "HIP runtime error";
     case TWOFOLD_EALIGN: return "data pointer not aligned to its element size";
     case TWOFOLD_EOFFSETS: return "segment offsets must start at 0 and not decrease";
+    case TWOFOLD_ENOTUNED: return "no measured launch for this configuration (default borrowed)";
+    case TWOFOLD_ECAPTURE: return "not allowed while a stream capture is under way";
     default: return "unknown status";
   }
 }

@@ -353,3 +353,109 @@ def test_batch_argument_checks():
                                            None) == 0
     assert L.twofold_workspace_bytes_batch(items((0x10000, 0x20000, 0x30000, 100, 4, 1, 3)), 1,
                                            None) > 0  # binary64 accumulator of binary32 data
+
+
+def test_status_codes_of_the_capture_and_tuning_paths():
+    from paper_1401_0248_amd._lib import ECAPTURE, ENOTUNED
+    L = _lib.load()
+    assert (ENOTUNED, ECAPTURE) == (-6, -7)
+    for code in (ENOTUNED, ECAPTURE):
+        msg = L.twofold_strerror(code)
+        assert msg and msg != L.twofold_strerror(12345), code
+
+
+def test_tuned_launch_reports_measured_rows():
+    """Every form the library has was timed by the autotuner for both call
+    kinds: twofold_tuned_launch returns OK and the default launch itself."""
+    import paper_1401_0248_amd as tf
+    L = _lib.load()
+    for kind in (0, 1):
+        for dt in (4, 8):
+            for dot in (0, 1):
+                for mode in range(8):
+                    if (mode in (5, 6) and not dot) or (mode == 7 and dt == 8):
+                        lc = Launch()
+                        assert L.twofold_tuned_launch(kind, dt, dot, mode, 100, 3,
+                                                      ctypes.byref(lc)) == EINVAL
+                        continue
+                    for n in (1, 1 << 20, 1 << 31):
+                        got, measured = tf.tuned_launch(kind, dt, dot, mode, n, 10)
+                        assert measured, (kind, dt, dot, mode, n)
+                        want = tf.default_launch(kind, dt, dot, mode, n, 10)
+                        assert got.as_dict() == want.as_dict()
+    assert L.twofold_tuned_launch(0, 4, 0, 0, 10, 0, None) == EINVAL
+
+
+def test_batch_item_reserved_must_be_zero():
+    from paper_1401_0248_amd._lib import BatchItem
+    L = _lib.load()
+    arr = (BatchItem * 1)()
+    arr[0].x, arr[0].y, arr[0].out, arr[0].n = 0x10000, 0x20000, 0x30000, 100
+    arr[0].dtype, arr[0].is_dot, arr[0].mode, arr[0].reserved = 8, 1, 2, 1
+    assert L.twofold_batch(arr, 1, None, ctypes.c_void_p(0x100000), 1 << 20, None) == EINVAL
+    assert L.twofold_workspace_bytes_batch(arr, 1, None) == 0
+
+
+SEG_GRID_PROBE = r"""
+#include <stdio.h>
+#include "kernels.hpp"
+int main() {
+  const long long ns[] = {0, 1, 3, 4, 5, 20000, 32767, 32768, 32769, 1LL << 26, 1LL << 34,
+                          1LL << 56};
+  for (long long n : ns) printf("%lld %lld\n", n, (long long)twofold::seg_pass2_blocks(n));
+  return 0;
+}
+"""
+
+
+def test_segment_combine_grid_is_capped_and_covers_every_segment(tmp_path):
+    """The per-segment combine kernel's grid (host arithmetic only): at most
+    8192 blocks of four waves for any segment count, and the waves' stride
+    loop (wave w takes segments w, w + 4*blocks, ...) reaches every segment
+    exactly once."""
+    src = tmp_path / "grid.hip"
+    src.write_text(SEG_GRID_PROBE)
+    exe = tmp_path / "grid"
+    r = subprocess.run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-std=c++17",
+                        "-I", os.path.join(ROOT, "paper_1401_0248_amd", "csrc"),
+                        "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    for line in out.split("\n"):
+        if not line:
+            continue
+        nseg, blocks = (int(v) for v in line.split())
+        assert 1 <= blocks <= 8192
+        assert blocks * 256 < 2 ** 32  # the x dimension of a launch
+        nw = blocks * 4
+        assert nw >= min(nseg, 8192 * 4)
+        if nseg <= 1 << 20:  # every segment once: waves w < nw take w, w + nw, ...
+            seen = np.zeros(nseg, dtype=np.int64)
+            for w in range(min(nw, nseg)):
+                seen[w::nw] += 1
+            assert (seen == 1).all()
+
+
+def test_launches_report_their_own_status():
+    """Every kernel launch of the library goes through launch_kernel, whose
+    status is the launch's own (hipLaunchKernel's result): no launch path
+    reads the thread's HIP error state, so an error left there by unrelated
+    code cannot fail a call between its kernels."""
+    csrc = os.path.join(ROOT, "paper_1401_0248_amd", "csrc")
+    for f in os.listdir(csrc):
+        if f.endswith((".hip", ".hpp")):
+            src = open(os.path.join(csrc, f)).read()
+            assert "<<<" not in src, f
+            if f == "segmented.hip":
+                # only plan creation's capture check touches the error state
+                # (to clear the errors of its own query and refused
+                # allocation), after its last launch-free host work
+                body = src[src.index("bool capture_under_way("):src.index("}  // namespace\n\n"
+                                                                          "// A plan owns")]
+                rest = src.replace(body, "")
+                assert "hipGetLastError" not in rest and "hipPeekAtLastError" not in \
+                    rest.replace("const bool state_was_clean = hipPeekAtLastError()", ""), f
+            else:
+                assert "hipGetLastError" not in src, f
+                assert "hipPeekAtLastError" not in src, f
