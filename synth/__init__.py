@@ -99,6 +99,34 @@ def uniform_chunks(seed, n, dtype, chunk=1 << 24):
         done += m
 
 
+def uniform_fill(seed, n, dtype, nthreads=None, out=None):
+    """The same n values as ``uniform(seed, n, dtype)`` (one array: x and y
+    of a dot drawn as one stream of 2n values), drawn by several threads.
+    Thread t draws positions [a_t, b_t) of the stream from its own copy of
+    the generator, advanced by a_t draws (PCG64's jump-ahead: one 64-bit
+    draw per value), so the result does not depend on the thread count."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    n = int(n)
+    dtype = np.dtype(dtype)
+    if out is None:
+        out = np.empty(n, dtype=dtype)
+    if nthreads is None:
+        nthreads = max(1, min(16, os.cpu_count() or 1))
+    chunk = 1 << 22
+    starts = list(range(0, n, chunk))
+
+    def part(a):
+        m = min(chunk, n - a)
+        bg = np.random.PCG64(seed)
+        bg.advance(a)
+        out[a:a + m] = raw_to_uniform(bg.random_raw(m), dtype)
+
+    with ThreadPoolExecutor(max_workers=nthreads) as ex:
+        list(ex.map(part, starts))
+    return out
+
+
 def scaled(seed, n, lo=-20, hi=20):
     """binary32 x, y with x = m * 2^k: m uniform(-1, 1), k uniform integer in
     [lo, hi]; draw order m_x, k_x, m_y, k_y. Every value is a multiple of
@@ -112,32 +140,43 @@ def scaled(seed, n, lo=-20, hi=20):
     return out[0], out[1]
 
 
-def _illcond_once(mx, my, kx, ky, n, h, dtype):
+def _illcond_once(mx, my, kx, ky, n, h, dtype, n_end=None):
+    """The recipe on [0, n_end) (default n): first half random exponents,
+    then the cancelling tail up to n_end. Elements from n_end on are left
+    for the caller."""
     half = n // 2
+    n_end = n if n_end is None else n_end
     x = np.empty(n, dtype=dtype)
     y = np.empty(n, dtype=dtype)
     x[:half] = np.ldexp(mx[:half], kx).astype(dtype)
     y[:half] = np.ldexp(my[:half], ky).astype(dtype)
-    mxt = np.ascontiguousarray(mx[half:], dtype=np.float64)
-    myt = np.ascontiguousarray(my[half:], dtype=np.float64)
+    mxt = np.ascontiguousarray(mx[half:n_end], dtype=np.float64)
+    myt = np.ascontiguousarray(my[half:n_end], dtype=np.float64)
     L = _clib()
     p_final = ctypes.c_double(0.0)
     if dtype == np.float64:
         tiny = 2.0 ** (-1022 + 53)
-        small = L.synth_illcond_tail_f64(x.ctypes.data, y.ctypes.data, half, n, mxt.ctypes.data,
-                                         myt.ctypes.data, h, tiny, ctypes.byref(p_final))
+        small = L.synth_illcond_tail_f64(x.ctypes.data, y.ctypes.data, half, n_end,
+                                         mxt.ctypes.data, myt.ctypes.data, h, tiny,
+                                         ctypes.byref(p_final))
     else:
         tiny = 2.0 ** (-126 + 24)
-        small = L.synth_illcond_tail_f32(x.ctypes.data, y.ctypes.data, half, n, mxt.ctypes.data,
-                                         myt.ctypes.data, h, tiny, ctypes.byref(p_final))
+        small = L.synth_illcond_tail_f32(x.ctypes.data, y.ctypes.data, half, n_end,
+                                         mxt.ctypes.data, myt.ctypes.data, h, tiny,
+                                         ctypes.byref(p_final))
     if small:
         raise ValueError("illcond_dot: %d products below the FMA-exactness range" % small)
-    if not (np.all(np.isfinite(x)) and np.all(np.isfinite(y))):
+    if not (np.all(np.isfinite(x[:n_end])) and np.all(np.isfinite(y[:n_end]))):
         raise ValueError("illcond_dot: non-finite value generated")
     return x, y, p_final.value
 
 
-def illcond_dot(seed, n, cond, dtype, calibrate=True):
+def _estimate_cond(x, y, p_final):
+    a = float(np.sum(np.abs(x.astype(np.float64) * y.astype(np.float64))))
+    return (2.0 * a / abs(p_final) if p_final != 0 else float("inf")), a
+
+
+def illcond_dot(seed, n, cond, dtype, calibrate=True, low_block=True):
     """Ill-conditioned dot-product inputs of length n (even, >= 4).
 
     b = log2(cond), h = round(b / 2). First half: x_i = m * 2^k and
@@ -151,7 +190,18 @@ def illcond_dot(seed, n, cond, dtype, calibrate=True):
     draws are used once more with h lowered by
     round(log2(estimate / cond) / 2), the estimate being
     2 * sum|x y| (binary64) / |final running dot| (x87 extended, rounded).
-    The exact achieved condition must still be measured by the caller."""
+
+    Even at h = 0 the recipe stays near n/2 or above (every cancelling step
+    adds a term of the size of the running dot, so sum|x y| grows like n
+    while the dot stays of order 1). For a lower target (``low_block``,
+    when the calibrated estimate still exceeds cond by more than 10^0.5)
+    the cancelling tail ends at n - n/16, and the last n/16 elements form a
+    non-cancelling block: x_i = m_i (the same draws), y_i = c * s *
+    sign(x_i) * |m'_i|, so every product has the sign s of the running dot
+    and the block adds T = sum|x y| over it, c chosen so that
+    2 (A + T) / (|P| + T) = cond, A and P being sum|x y| and the running
+    dot before the block. The exact achieved condition must still be
+    measured by the caller."""
     if n < 4 or n % 2:
         raise ValueError("illcond_dot: n must be even and >= 4")
     dtype = np.dtype(dtype)
@@ -166,13 +216,28 @@ def illcond_dot(seed, n, cond, dtype, calibrate=True):
         kx = raw_to_int(ux, 0, h).astype(np.int32)
         ky = raw_to_int(uy, 0, h).astype(np.int32)
         x, y, p_final = _illcond_once(mx, my, kx, ky, n, h, dtype)
+        est, _ = _estimate_cond(x, y, p_final)
         if attempt == 0 and calibrate:
-            a = float(np.sum(np.abs(x.astype(np.float64) * y.astype(np.float64))))
-            est = 2.0 * a / abs(p_final) if p_final != 0 else float("inf")
             delta = int(round(np.log2(est / float(cond)) / 2.0)) if np.isfinite(est) else 0
             if delta <= 0:
                 break
             h = max(0, h - delta)
+    if low_block and calibrate and est > float(cond) * 10 ** 0.5 and n >= 64:
+        m = n // 16
+        n_end = n - m
+        x, y, p_ill = _illcond_once(mx, my, kx, ky, n, h, dtype, n_end=n_end)
+        _, a_ill = _estimate_cond(x[:n_end], y[:n_end], 1.0)
+        t = (2.0 * a_ill - float(cond) * abs(p_ill)) / (float(cond) - 2.0)
+        if t > 0:
+            s = 1.0 if p_ill >= 0 else -1.0
+            xb = mx[n_end:].astype(dtype)
+            base = np.abs(xb.astype(np.float64) * my[n_end:].astype(np.float64))
+            c = t / float(np.sum(base)) if np.sum(base) > 0 else 0.0
+            x[n_end:] = xb
+            y[n_end:] = (s * c * np.sign(xb.astype(np.float64)) *
+                         np.abs(my[n_end:].astype(np.float64))).astype(dtype)
+        else:  # the cancelling part alone already meets the target
+            x, y, _ = _illcond_once(mx, my, kx, ky, n, h, dtype)
     return x, y
 
 

@@ -8,6 +8,8 @@ import pytest
 import oracle
 import synth
 
+DECADES = (6, 8, 10, 12, 14, 16)
+
 
 def _h(*arrs):
     m = hashlib.sha256()
@@ -52,14 +54,37 @@ def test_segment_lengths_cfg():
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_illcond_reaches_its_decade(dtype):
-    for d in (6, 10, 16):
-        x, y = synth.illcond_dot(synth.illcond_seed(d), 1 << 16, 10.0 ** d, dtype)
+    """At the configuration's N = 2^24, every target decade 1e6 .. 1e16 is
+    reached within a factor of 10 (exact condition 2 sum|x y| / |sum x y|
+    from the exact accumulator); the draws are reproducible."""
+    for d in DECADES:
+        x, y = synth.illcond_dot(synth.illcond_seed(d), 1 << 24, 10.0 ** d, dtype)
         ex = oracle.Exact(x, y)
         cond = 2 * ex.A / abs(ex.S)
-        assert 10.0 ** (d - 1.5) < cond < 10.0 ** (d + 1.5), (d, cond)
-        x2, y2 = synth.illcond_dot(synth.illcond_seed(d), 1 << 16, 10.0 ** d, dtype)
-        assert _h(x, y) == _h(x2, y2)
+        assert 10.0 ** (d - 1) < cond < 10.0 ** (d + 1), (d, cond)
         assert np.all(np.isfinite(x)) and np.all(np.isfinite(y))
+    x, y = synth.illcond_dot(synth.illcond_seed(8), 1 << 16, 1e8, dtype)
+    x2, y2 = synth.illcond_dot(synth.illcond_seed(8), 1 << 16, 1e8, dtype)
+    assert _h(x, y) == _h(x2, y2)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_illcond_low_block(dtype):
+    """Below what the cancelling recipe reaches, the last n/16 elements are
+    the non-cancelling block: every product there has the sign of the dot of
+    the elements before it, and the earlier elements are the recipe's own
+    (the block changes nothing before it)."""
+    n = 1 << 16
+    x, y = synth.illcond_dot(synth.illcond_seed(6), n, 1e6 / 64, dtype)
+    x0, y0 = synth.illcond_dot(synth.illcond_seed(6), n, 1e6 / 64, dtype, low_block=False)
+    m = n // 16
+    head = oracle.Exact(x[:n - m], y[:n - m])
+    p = x[n - m:].astype(np.float64) * y[n - m:].astype(np.float64)
+    assert np.all(p * head.sign >= 0) and np.count_nonzero(p) > m // 2
+    assert _h(x[:n // 2], y[:n // 2]) == _h(x0[:n // 2], y0[:n // 2])
+    ex = oracle.Exact(x, y)
+    cond = 2 * ex.A / abs(ex.S)
+    assert 1e6 / 64 / 10 < cond < 1e6 / 64 * 10, cond
 
 
 def test_hundred_hours_input():
@@ -78,3 +103,14 @@ def test_permuted_illcond_keeps_the_exact_dot():
         assert sorted((x.astype(np.float64) * y).tolist()) == sorted((px.astype(np.float64) * py).tolist())
         a, b = oracle.Exact(x, y), oracle.Exact(px, py)
         assert a.S == b.S and a.diff(a.S) == b.diff(a.S) and a.A == b.A
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_uniform_fill_is_the_serial_stream(dtype):
+    """The threaded generator (jump-ahead per chunk) draws exactly the serial
+    stream, for any thread count, across chunk boundaries and a ragged end."""
+    n = (1 << 23) + 12345
+    want = synth.uniform(3, n, dtype)
+    for nt in (1, 3, 8):
+        got = synth.uniform_fill(3, n, dtype, nthreads=nt)
+        assert got.dtype == dtype and _h(got) == _h(want), nt
