@@ -16,10 +16,22 @@ def pytest_configure(config):
         # copies, tests/test_oracle_mutants.py)
         from oracle import build as oracle_build
         oracle_build.build = lambda force=False, quiet=True: lib
+    bounds_py = os.environ.get("TWOFOLD_BOUNDS_PY")
+    if bounds_py:
+        # the bound pins run against another copy of oracle/bounds.py
+        # (planted-mistake copies, tests/test_oracle_mutants.py)
+        import importlib.util
+
+        import oracle
+        spec = importlib.util.spec_from_file_location("oracle.bounds", bounds_py)
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        sys.modules["oracle.bounds"] = mod
+        oracle.bounds = mod
 
 
 def _have_gpu():
-    if os.environ.get("TWOFOLD_ORACLE_LIB"):
+    if os.environ.get("TWOFOLD_ORACLE_LIB") or os.environ.get("TWOFOLD_BOUNDS_PY"):
         return False  # CPU-only runs of the oracle's pins
     try:
         import torch

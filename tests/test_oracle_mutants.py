@@ -111,6 +111,36 @@ MUTANTS = [
 ]
 
 
+# Slips in the error bounds (oracle/bounds.py), run against the bound pins
+# (the bound tests pin each bound from below and from above).
+BOUND_PIN_FILES = ["tests/test_bounds.py", "tests/test_model.py", "tests/test_mixed.py"]
+BOUND_MUTANTS = [
+    ("double-word bound: u for u^2", "3 * u * u + 13 * u ** 3", "3 * u + 13 * u ** 3"),
+    ("fast loss term dropped", "loss = u * (1 + 2 * u) * fast_violations",
+     "loss = 0.0 * fast_violations"),
+    ("fast loss term: u^2 for u", "loss = u * (1 + 2 * u) * fast_violations",
+     "loss = u * u * fast_violations"),
+    ("tree bound: factor u dropped from the terms", "T = u * (Lc + D + 1) * grow * A + loss",
+     "T = (Lc + D + 1) * grow * A + loss"),
+    ("tree bound 10^4 too tight", "b = g(h, u) * T + loss", "b = 1e-4 * g(h, u) * T + loss"),
+    ("mixed bound: binary32 rounding for the binary64 error sum", "return g(h, u64) * T + u64 *",
+     "return g(h, u32) * T + u64 *"),
+]
+
+
+def _bound_mutant(tmp, i, name, text, repl):
+    src = open(os.path.join(ROOT, "oracle", "bounds.py")).read()
+    assert src.count(text) == 1, (name, src.count(text))
+    path = os.path.join(tmp, "bounds_m%02d.py" % i)
+    with open(path, "w") as f:
+        f.write(src.replace(text, repl))
+    env = dict(os.environ, TWOFOLD_BOUNDS_PY=path, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu",
+                        "-p", "no:cacheprovider"] + BOUND_PIN_FILES,
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return r.returncode, (r.stdout + r.stderr)[-1500:]
+
+
 def _sources(dst):
     for f in obuild.DEPS:
         shutil.copy(os.path.join(obuild.HERE, f), os.path.join(dst, f))
@@ -165,4 +195,17 @@ def test_every_planted_mistake_fails_a_pin(tmp):
         futs = [pool.submit(_mutant, tmp, i, *m) for i, m in enumerate(MUTANTS)]
         results = [f.result() for f in futs]
     survivors = [(m[0], tail) for m, (rc, tail) in zip(MUTANTS, results) if rc != 1]
+    assert not survivors, survivors
+
+
+def test_unchanged_bounds_copy_passes_the_bound_pins(tmp):
+    rc, tail = _bound_mutant(tmp, 99, "unchanged", "import math", "import math")
+    assert rc == 0, tail
+
+
+def test_every_planted_bound_mistake_fails_a_pin(tmp):
+    with ThreadPoolExecutor(max_workers=4) as pool:
+        futs = [pool.submit(_bound_mutant, tmp, i, *m) for i, m in enumerate(BOUND_MUTANTS)]
+        results = [f.result() for f in futs]
+    survivors = [(m[0], tail) for m, (rc, tail) in zip(BOUND_MUTANTS, results) if rc != 1]
     assert not survivors, survivors
