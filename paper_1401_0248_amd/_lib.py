@@ -92,7 +92,9 @@ _lib = None
 
 
 def lib_path():
-    return _build.LIB
+    # TWOFOLD_HIP_LIB: another build of the library (the host-sanitizer
+    # test's), used as is
+    return os.environ.get("TWOFOLD_HIP_LIB") or _build.LIB
 
 
 def load():
@@ -100,8 +102,8 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    path = _build.LIB
-    if not os.path.exists(path):
+    path = lib_path()
+    if path == _build.LIB and not os.path.exists(path):
         _build.build()
     try:
         L = ctypes.CDLL(path)

@@ -43,7 +43,8 @@ def build(force=False):
 def _clib():
     global _lib
     if _lib is None:
-        L = ctypes.CDLL(build())
+        # TWOFOLD_SYNTH_LIB: another build of illcond.c (the sanitizer test's)
+        L = ctypes.CDLL(os.environ.get("TWOFOLD_SYNTH_LIB") or build())
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         for nm in ("synth_illcond_tail_f64", "synth_illcond_tail_f32"):
             f = getattr(L, nm)
