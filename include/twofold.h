@@ -328,6 +328,23 @@ size_t twofold_workspace_bytes_batch(const twofold_batch_item_t* items, int64_t 
 int twofold_batch(const twofold_batch_item_t* items, int64_t count,
                   const twofold_launch_t* launch, void* ws, size_t ws_bytes, void* stream);
 
+/* twofold_batch without a workspace, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. Items, launch, stream and results are
+ * those of twofold_batch (each pair bitwise twofold_batch's with the same
+ * launch); nothing is allocated or freed and no allocating library routine
+ * is called. The block pairs go to a static device array of
+ * TWOFOLD_STATIC_SCRATCH_BYTES (4 MiB) that each device holds until the
+ * process ends; the first call on a device looks its address up
+ * (hipGetSymbolAddress) with that device current. A batch whose block pairs
+ * need more (16 * count * grid_blocks bytes when grid_blocks > 1; e.g. 64
+ * items of 4096 blocks) returns TWOFOLD_EWORKSPACE before any HIP call.
+ * All calls on one device share the array and nothing in it outlives a
+ * call: calls that can overlap on one device (on different streams, or
+ * graphs replayed concurrently) race and must be ordered by the caller. */
+#define TWOFOLD_STATIC_SCRATCH_BYTES (4u << 20)
+int twofold_batch_static(const twofold_batch_item_t* items, int64_t count,
+                         const twofold_launch_t* launch, void* stream);
 
 /* ---- segmented (CSR) batches: nseg pairs into out[0..nseg) ---------------
  * offsets: device int64[nseg + 1], non-decreasing, offsets[0] >= 0 and

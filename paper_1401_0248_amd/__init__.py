@@ -290,6 +290,18 @@ def batch(items, launch=None, outs=None, ws=None):
     return res
 
 
+def batch_static(items, launch=None, outs=None):
+    """batch() without a workspace (twofold_batch_static): the block pairs
+    go to the library's static per-device scratch of 4 MiB, so the call
+    allocates nothing (torch included, when outs are given). Calls that can
+    overlap on one device race on that scratch."""
+    L = _lib.load()
+    arr, count, res, dev = _batch_items(items, outs)
+    check("twofold_batch_static", L.twofold_batch_static(
+        ctypes.cast(arr, ctypes.c_void_p), count, _launch_ptr(launch), _stream_ptr(dev)))
+    return res
+
+
 def _batch_items(items, outs):
     """The twofold_batch_item_t array of a batch, and its output tensors."""
     items = list(items)

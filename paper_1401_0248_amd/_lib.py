@@ -78,6 +78,7 @@ SIGNATURES = {
     "twofold_probe_compute": (_int, [_int, _int, _int, _vp, _i64, _LP, _vp, _vp]),
     "twofold_workspace_bytes_batch": (_sz, [_vp, _i64, _LP]),
     "twofold_batch": (_int, [_vp, _i64, _LP, _vp, _sz, _vp]),
+    "twofold_batch_static": (_int, [_vp, _i64, _LP, _vp]),
     "twofold_strerror": (ctypes.c_char_p, [_int]),
 }
 

@@ -8,6 +8,8 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 #include "host_common.hpp"
 #include "kernels.hpp"
 #include "twofold.h"
@@ -229,9 +231,37 @@ size_t twofold_workspace_bytes_batch(const twofold_batch_item_t* items, int64_t 
 
 namespace {
 
-// twofold_batch: the block pairs in ws.
+// The block pairs of twofold_batch_static: one array per device, in device
+// memory for the life of the process. Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in): the address each
+// device gives the array comes from hipGetSymbolAddress, looked up on the
+// first call on that device and kept per device.
+constexpr size_t kStaticScratchBytes = size_t(TWOFOLD_STATIC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// The current device's address of scratch (set up once per device).
+int static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return TWOFOLD_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return TWOFOLD_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TWOFOLD_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TWOFOLD_OK;
+}
+
+// twofold_batch with its block pairs in ws, or (ws_static) in the device's
+// static scratch.
 int batch_common(const twofold_batch_item_t* items, int64_t count, const twofold_launch_t* launch,
-                 void* ws, size_t ws_bytes, void* stream) {
+                 void* ws, size_t ws_bytes, bool ws_static, void* stream) {
   twofold_launch_t lc;
   int64_t max_bytes = 0;
   const int rc = resolve_batch(items, count, launch, &lc, &max_bytes);
@@ -258,8 +288,14 @@ int batch_common(const twofold_batch_item_t* items, int64_t count, const twofold
   }
   for (int64_t v = count; v < kMaxBatch; v++) a.e[v] = BatchEntry{nullptr, nullptr, nullptr, 0, 0};
   if (count == 0) return TWOFOLD_OK;
-  if (lc.grid_blocks > 1 && !ws_ok(ws, ws_bytes, multi_ws_bytes(lc, count)))
+  if (ws_static) {
+    if (lc.grid_blocks > 1 && multi_ws_bytes(lc, count) > kStaticScratchBytes)
+      return TWOFOLD_EWORKSPACE;
+    const int rs = static_scratch(&ws);
+    if (rs) return rs;
+  } else if (lc.grid_blocks > 1 && !ws_ok(ws, ws_bytes, multi_ws_bytes(lc, count))) {
     return TWOFOLD_EWORKSPACE;
+  }
   const int sets = max_bytes <= kBatchSideBytes ? int(count) : 1;
   double* part = static_cast<double*>(ws);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -272,7 +308,12 @@ extern "C" {
 
 int twofold_batch(const twofold_batch_item_t* items, int64_t count,
                   const twofold_launch_t* launch, void* ws, size_t ws_bytes, void* stream) {
-  return batch_common(items, count, launch, ws, ws_bytes, stream);
+  return batch_common(items, count, launch, ws, ws_bytes, false, stream);
+}
+
+int twofold_batch_static(const twofold_batch_item_t* items, int64_t count,
+                         const twofold_launch_t* launch, void* stream) {
+  return batch_common(items, count, launch, nullptr, 0, true, stream);
 }
 
 }  // extern "C"
