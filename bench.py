@@ -876,6 +876,55 @@ def probes(np, torch, tf, dev):
                       "rows": rows}), flush=True)
 
 
+def single_calls(np, torch, tf, dev):
+    """Per-call cost of the single-vector path: the binary64 rigorous dot of
+    N = 2^24 uniform(-1, 1) pairs (seed 0) at its default launch, 50 calls
+    back to back, as one HIP-graph replay and as eager launches; per-call
+    time by events around all 50. Under a kernel trace the dispatches show
+    how a call's time splits into the reduce kernel, the gap before the
+    combine kernel, the combine and the gap before the next call. One JSON
+    line."""
+    import synth
+    n = 1 << 24
+    both = torch.from_numpy(synth.uniform_fill(0, 2 * n, np.float64,
+                                               nthreads=worker_threads())).to(dev)
+    x, y = both[:n], both[n:]
+    lc = tf.default_launch(0, 8, True, "rigorous", n)
+    out = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = tf.Workspace(1 << 20, dev)
+    calls = 50
+
+    def run():
+        for _ in range(calls):
+            tf.dot(x, y, "rigorous", lc, out=out, ws=ws)
+        return calls
+
+    t_graph, t_graph_min = graph_time(torch, run, reps=10)
+    st = torch.cuda.current_stream(dev)
+    ts = []
+    for _ in range(10):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        run()
+        e1.record(st)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3 / calls)
+    import statistics
+    t_eager = statistics.median(ts)
+    nbytes = 2 * n * 8
+    res = {"workload": "single-vector binary64 rigorous dot, N=2^24 (256 MiB per call), "
+                       "50 calls back to back", "launch": lc.as_dict(),
+           "graph_us_per_call": round(t_graph * 1e6, 2),
+           "graph_frac": round(nbytes / t_graph / 1e9 / HBM_PEAK_GBS, 4),
+           "eager_us_per_call": round(t_eager * 1e6, 2),
+           "eager_frac": round(nbytes / t_eager / 1e9 / HBM_PEAK_GBS, 4),
+           "device": device_info(torch, dev)}
+    log("single calls: graph %.2f us/call (%.3f), eager %.2f us/call (%.3f)"
+        % (t_graph * 1e6, res["graph_frac"], t_eager * 1e6, res["eager_frac"]))
+    print(json.dumps(res), flush=True)
+
+
 COPY_BYTES = 1 << 28
 
 
@@ -935,13 +984,14 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     ap.add_argument("--workload", choices=("headline", "illcond", "sweep", "segmented",
-                                           "precision", "probes"),
+                                           "precision", "probes", "single"),
                     default="headline",
                     help="headline: the default line (20,000-segment batch with the other "
                          "configurations as sub-objects); illcond: the ill-conditioned batch "
                          "alone; sweep: every form at 4096, 2^20 and 1 GiB per vector; "
                          "segmented: both segment batches and the monitor; precision: binary32 "
-                         "twofold against binary64 plain at N=2^26; probes: the instruments")
+                         "twofold against binary64 plain at N=2^26; probes: the instruments; "
+                         "single: the per-call cost of single-vector dots")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library's reduction runs on one device "
@@ -971,6 +1021,9 @@ def main():
         return
     if args.workload == "probes":
         probes(np, torch, tf, dev)
+        return
+    if args.workload == "single":
+        single_calls(np, torch, tf, dev)
         return
     if args.workload == "illcond":
         res = illcond_batch(np, torch, tf, dev, args.steps, args.warmup, with_oracle)

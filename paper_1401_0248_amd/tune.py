@@ -80,11 +80,18 @@ def time_graph(calls, reps=7):
     return statistics.median(out)
 
 
-def single_candidates(quick):
+def spills(bt, u, is_dot):
+    """Launch shapes whose kernel instance spills registers: eight-vector
+    dots in the instance built for blocks of more than 512 threads (128
+    VGPRs). The table never picks them."""
+    return bool(is_dot) and u == 8 and bt > 512
+
+
+def single_candidates(quick, is_dot=0):
     bts = (256, 512) if quick else (256, 512, 1024)
     us = (2, 4, 8) if quick else (1, 2, 4, 8)
     gbs = (256, 512) if quick else (128, 256, 512, 1024, 2048)
-    return list(itertools.product(bts, us, gbs))
+    return [c for c in itertools.product(bts, us, gbs) if not spills(c[0], c[1], is_dot)]
 
 
 def tune_single(dev, quick, combos, only_buckets=None, passes=1):
@@ -133,7 +140,7 @@ def tune_single(dev, quick, combos, only_buckets=None, passes=1):
             # every pass times all candidates, in alternating order; a
             # candidate keeps its best time, so one slow replay does not
             # decide
-            cands = single_candidates(quick)
+            cands = single_candidates(quick, is_dot)
             times = {}
             for p in range(passes):
                 for c in (cands if p % 2 == 0 else cands[::-1]):
@@ -173,6 +180,8 @@ def tune_seg(dev, quick, combos):
                                       (256, 512) if quick else (256, 512, 1024),
                                       (256, 1024) if quick else (256, 512, 1024))
             for tm, u, bt, gb in cands:
+                if spills(bt, u, is_dot):
+                    continue
                 lc = tf.Launch(bt, u, gb, 0, 64 * W * tm)
                 plan = tf.SegPlan(off, tdt, is_dot, MODES[mode], lc)
                 out = torch.empty((plan.nseg, 2), dtype=plan.out_dtype, device=dev)
