@@ -208,52 +208,62 @@ __device__ __forceinline__ void combine(A& s1, A& e1, A s2, A e2) {
   }
 }
 
-// ---- cross-lane moves: the value held by lane (lane xor D) ----------------
-// D = 1, 2: DPP quad permutations; D = 4, 8, 16: ds_swizzle in bit-mask mode
-// (lane' = lane xor mask within 32 lanes); D = 32: ds_bpermute.
+// ---- wave combine ---------------------------------------------------------
+// Lane l receives the value of lane l - D: within its row of 16 lanes for
+// D = 1, 2, 4, 8 (DPP row_shr), from lane 15 of the row before for D = 16
+// (row_bcast:15, rows 1 and 3 written) and from lane 31 for D = 32
+// (row_bcast:31, rows 2 and 3 written). Only the top lane of each group of
+// 2D lanes uses the value, and for it the source lane is always valid. All
+// moves are VALU data-parallel operations: no LDS access, so nothing waits
+// on the LDS/scalar-memory counter.
 template <int D>
-__device__ __forceinline__ int xor_lane_b32(int v) {
-  if constexpr (D == 1) {
-    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
-  } else if constexpr (D == 2) {
-    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
-  } else if constexpr (D == 4 || D == 8 || D == 16) {
-    return __builtin_amdgcn_ds_swizzle(v, (D << 10) | 0x1F);
+__device__ __forceinline__ int from_lower_b32(int v) {
+  if constexpr (D <= 8) {
+    return __builtin_amdgcn_mov_dpp(v, 0x110 + D, 0xF, 0xF, false);
+  } else if constexpr (D == 16) {
+    return __builtin_amdgcn_mov_dpp(v, 0x142, 0xA, 0xF, false);
   } else {
-    static_assert(D == 32, "xor distance");
-    const int lane = __lane_id();
-    return __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
+    static_assert(D == 32, "distance");
+    return __builtin_amdgcn_mov_dpp(v, 0x143, 0xC, 0xF, false);
   }
 }
 
 template <int D>
-__device__ __forceinline__ float xor_lane(float v) {
-  return __int_as_float(xor_lane_b32<D>(__float_as_int(v)));
+__device__ __forceinline__ float from_lower(float v) {
+  return __int_as_float(from_lower_b32<D>(__float_as_int(v)));
 }
 
 template <int D>
-__device__ __forceinline__ double xor_lane(double v) {
+__device__ __forceinline__ double from_lower(double v) {
   const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
-  const int lo = xor_lane_b32<D>(static_cast<int>(static_cast<uint32_t>(u)));
-  const int hi = xor_lane_b32<D>(static_cast<int>(static_cast<uint32_t>(u >> 32)));
+  const int lo = from_lower_b32<D>(static_cast<int>(static_cast<uint32_t>(u)));
+  const int hi = from_lower_b32<D>(static_cast<int>(static_cast<uint32_t>(u >> 32)));
   const uint64_t r = (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
                      static_cast<uint64_t>(static_cast<uint32_t>(lo));
   return __longlong_as_double(static_cast<long long>(r));
 }
 
+// The top lane of each group of 2D lanes replaces its pair by
+// combine(pair of lane l - D, own pair): the lower group's pair first.
 template <int M, int D, typename A>
 __device__ __forceinline__ void wave_stage(A& s, A& e) {
-  const A s2 = xor_lane<D>(s);
-  if constexpr (!has_error(M)) {
-    combine<M>(s, e, s2, A(0));
-  } else {
-    const A e2 = xor_lane<D>(e);
-    combine<M>(s, e, s2, e2);
-  }
+  A ls = from_lower<D>(s);
+  A le = has_error(M) ? from_lower<D>(e) : A(0);
+  combine<M>(ls, le, s, e);
+  s = ls;
+  e = le;
 }
 
-// Wave combine: xor distances 1, 2, 4, 8, 16, 32 in this order; every lane
-// computes combine(own, partner). All 64 lanes must be active.
+// The lane that holds a wave's combined pair.
+constexpr int kWaveRoot = 63;
+
+// Wave combine (step 5): distances 1, 2, 4, 8, 16, 32 in this order. After
+// the stage of distance D the top lane of each aligned group of 2D lanes
+// holds combine(lower D lanes, upper D lanes), each half combined the same
+// way, so lane kWaveRoot ends with the pair that lane 0 holds after the
+// documented exchange (where lane l combines its pair with lane l xor D's,
+// its own first): both are the balanced binary tree over lanes 0..63 with
+// the lower half's pair first in every combine. All 64 lanes must be active.
 template <int M, typename A>
 __device__ __forceinline__ void wave_combine(A& s, A& e) {
   wave_stage<M, 1>(s, e);

@@ -3,7 +3,7 @@
 // Streaming reductions bound by HBM bandwidth: 16-byte vector loads
 // (global_load_dwordx4), U independent loads in flight per lane, W = 16 /
 // sizeof(T) independent (s, e) chains per lane, then pair combines across
-// chains, lanes (DPP / ds_swizzle / ds_bpermute), waves (LDS) and blocks
+// chains, lanes (DPP), waves (LDS) and blocks
 // (binary64, in one fixed order). No matrix cores: there is no contraction
 // to feed them. The order is the one documented in include/twofold.h; it
 // depends only on the launch configuration and the inputs, so results are
@@ -285,7 +285,7 @@ __device__ __forceinline__ void block_store(A s, A e, double* __restrict__ part,
   wave_combine<M>(s, e);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nw = blockDim.x >> 6;
-  if (lane == 0) {
+  if (lane == kWaveRoot) {
     sh_s[wave] = s;
     sh_e[wave] = e;
   }
@@ -382,7 +382,7 @@ __device__ __forceinline__ void pass2_block(const double2* __restrict__ pairs, i
   combine_strided<P>(pairs, nparts, threadIdx.x, kPass2Lanes, qs, qe);
   wave_combine<P>(qs, qe);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) {
+  if (lane == kWaveRoot) {
     sh_s[wave] = qs;
     sh_e[wave] = qe;
   }
@@ -458,7 +458,7 @@ template <typename T, typename A, int M>
 __device__ __forceinline__ void tile_store(A s, A e, int lane, int64_t t, int64_t sg, int64_t ntl,
                                            double* __restrict__ slots, void* __restrict__ out) {
   wave_combine<M>(s, e);
-  if (lane == 0) {
+  if (lane == kWaveRoot) {
     if (ntl == 1)
       finalize_store<T, M>(out, sg, static_cast<double>(s), static_cast<double>(e));
     else
@@ -623,11 +623,20 @@ __device__ __forceinline__ void seg_tiles_ahead(const T* __restrict__ x, const T
 
 
 // Which wave takes which tile does not change any result; the assignment
-// balances bytes. A tile costs its length plus c0 = 64*W*U elements (one
-// round of its wave, standing for the tile's start-up), so the tiles before
-// segment s cost cbase(s) = (off[s] - off[0]) + c0*tbase[s], and the total
-// is C = cbase(nseg). Wave w of NW takes the tiles whose start cost lies in
-// [floor(w*C/NW), floor((w+1)*C/NW)).
+// balances time. A tile costs its length plus c0 elements, c0 standing for
+// its start-up and finish (the first loads' round trip, the combine and the
+// store): measured on MI355X as about as long as streaming 16 KiB of input,
+// whatever the unroll (a sweep of c0 on batches of 20,000 log-uniform
+// segments put the best balance at 12-32 KiB for both data types). So
+// c0 = kSegTileCostBytes / (bytes of one element position), the tiles
+// before segment s cost cbase(s) = (off[s] - off[0]) + c0*tbase[s], and the
+// total is C = cbase(nseg). Wave w of NW takes the tiles whose start cost
+// lies in [floor(w*C/NW), floor((w+1)*C/NW)).
+constexpr int64_t kSegTileCostBytes = 16384;
+
+constexpr int64_t seg_tile_cost(int64_t elem_bytes, bool dot) {
+  return kSegTileCostBytes / (elem_bytes * (dot ? 2 : 1));
+}
 __device__ __forceinline__ int64_t seg_cost_bound(int64_t w, int64_t C, int64_t NW) {
   return static_cast<int64_t>((static_cast<__int128>(w) * C) / NW);
 }
@@ -658,7 +667,7 @@ seg_kernel(const T* __restrict__ x, const T* __restrict__ y, const int64_t* __re
     sg = wtab[2 * w + 1];
     t1 = wtab[2 * w + 2];
   } else {
-    constexpr int64_t c0 = 64 * (16 / static_cast<int64_t>(sizeof(T))) * U;
+    constexpr int64_t c0 = seg_tile_cost(sizeof(T), DOT);
     const int64_t NW = static_cast<int64_t>(gridDim.x) * wpb;
     const int64_t o0 = off[0];
     const int64_t C = (off[nseg] - o0) + c0 * tbase[nseg];
@@ -750,7 +759,7 @@ seg_pass2_kernel(const int64_t* __restrict__ tbase, int64_t nseg,
     double qs = 0.0, qe = 0.0;
     combine_strided<P>(reinterpret_cast<const double2*>(slots) + tb, ntl, lane, 64, qs, qe);
     wave_combine<P>(qs, qe);
-    if (lane == 0) finalize_store<T, M>(out, sg, qs, qe);
+    if (lane == kWaveRoot) finalize_store<T, M>(out, sg, qs, qe);
   }
 }
 

@@ -37,7 +37,7 @@ read_probe_kernel(const float* __restrict__ x, const float* __restrict__ y, int6
       x, y, n, 0, L, g, s, e);
   wave_combine<kProbeOr>(s, e);
   __shared__ uint32_t sh[16];
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = __float_as_uint(s);
+  if ((threadIdx.x & 63) == kWaveRoot) sh[threadIdx.x >> 6] = __float_as_uint(s);
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t r = 0;

@@ -150,7 +150,7 @@ constexpr int64_t kMaxPlanWaves = int64_t(1) << 20;
 // wt[2w] = the first tile whose start cost is at least floor(w*C/NW) and
 // wt[2w+1] = the segment holding that tile (the last segment when the tile
 // index is NT). Same cost model as the kernel's own search: a tile costs its
-// length plus c0 = 64*W*U elements.
+// length plus c0 = seg_tile_cost elements.
 void build_wave_table(const int64_t* off, const int64_t* tb, int64_t nseg, int64_t ts, int64_t c0,
                       int64_t nw, int64_t* wt) {
   const int64_t C = (off[nseg] - off[0]) + c0 * tb[nseg];
@@ -332,8 +332,9 @@ int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype
     wbytes = sizeof(int64_t) * size_t(2 * (nw + 1));
     wt = static_cast<int64_t*>(malloc(wbytes));
     ok = wt != nullptr;
-    if (ok) build_wave_table(offsets_host, tb, nseg, lc.tile_elems, 64 * (16 / dtype) * lc.unroll,
-                             nw, wt);
+    if (ok)
+      build_wave_table(offsets_host, tb, nseg, lc.tile_elems, seg_tile_cost(dtype, is_dot != 0),
+                       nw, wt);
   }
   // the first failing HIP call's error, if any
   hipError_t he = hipSuccess;
