@@ -57,14 +57,21 @@ __device__ __forceinline__ double fma_rn(double a, double b, double c) { return 
 // arithmetic", ACM TOMS 2017): DWPlusFP (their Algorithm 4, relative error
 // at most 2u^2) and AccurateDWPlusDW (their Algorithm 6, at most
 // 3u^2 + 13u^3), built from two-sum (Theorem 2) and fast-two-sum (Theorem 1).
-__device__ __forceinline__ void two_sum(double a, double b, double& s, double& d) {
+// Knuth's two-sum (Theorem 2): s = fl(a + b) and the exact remainder
+// d = (a - av) + (b - bv), where bv = s - a and av = s - bv are the parts of
+// s that came from b and from a; s + d = a + b for any finite a, b.
+template <typename F>
+__device__ __forceinline__ void two_sum(F a, F b, F& s, F& d) {
   s = a + b;
-  const double bp = s - a;
-  const double ap = s - bp;
-  d = (a - ap) + (b - bp);
+  const F bv = s - a;
+  const F av = s - bv;
+  d = (a - av) + (b - bv);
 }
 
-__device__ __forceinline__ void fast_two_sum(double a, double b, double& s, double& d) {
+// Dekker's fast-two-sum (Theorem 1): s = fl(a + b), d = b - (s - a);
+// s + d = a + b when |a| >= |b|.
+template <typename F>
+__device__ __forceinline__ void fast_two_sum(F a, F b, F& s, F& d) {
   s = a + b;
   d = b - (s - a);
 }
@@ -111,61 +118,46 @@ __device__ __forceinline__ void step(A& s, A& e, T xv, T yv) {
       dw_add_fp(s, e, xv);
     }
   } else if constexpr (M == kMixed) {
-    // Example 3 in binary32 on the value; its exact round-off ds + dy and
-    // the product remainder join the binary64 error
+    // the rigorous step in binary32 on the value; its exact remainder and
+    // the product's join the binary64 error
     static_assert(sizeof(T) == 4 && sizeof(A) == 8, "mixed: binary32 data, binary64 registers");
-    const float sf = static_cast<float>(s);  // exact: s holds a binary32 number
     const float p = DOT ? xv * yv : xv;
-    const float t = sf + p;
-    const float yt = t - sf;
-    const float dy = p - yt;
-    const float ds = sf - (t - yt);
+    float t, r;
+    two_sum(static_cast<float>(s), p, t, r);  // s holds a binary32 number: exact
     if constexpr (DOT) {
-      const float pi = fma_rn(xv, yv, -p);
-      e = e + (static_cast<double>(ds + dy) + static_cast<double>(pi));
+      e = e + (static_cast<double>(r) + static_cast<double>(fma_rn(xv, yv, -p)));
     } else {
-      e = e + static_cast<double>(ds + dy);
+      e = e + static_cast<double>(r);
     }
     s = static_cast<double>(t);
   } else if constexpr (M == kPlain) {
     T item = DOT ? xv * yv : xv;
     s = s + item;
   } else if constexpr (M == kKahan) {
-    // Example 2 with e holding -c, the negated correction: item - c is
-    // item + e and the new -c is yk - (t - s), both exactly the negations
-    // of the paper's operations.
-    T item = DOT ? xv * yv : xv;
-    T yk = item + e;
-    T t = s + yk;
-    e = yk - (t - s);
-    s = t;
+    // Example 2 with e holding the negated correction: the item corrected
+    // by e, then fast-two-sum of the value and the corrected item, whose
+    // remainder is the next negated correction.
+    const T item = DOT ? xv * yv : xv;
+    fast_two_sum(s, item + e, s, e);
   } else {
-    constexpr bool kTrack = DOT && (M == kFast || M == kRigorous);  // FMA remainder
+    // The twofold steps: the value takes the item (a dot's rounded product
+    // p); the error takes the step's remainder, from fast-two-sum (fast
+    // form, Example 1: exact when |s| >= |item|) or two-sum (rigorous form,
+    // Example 3: exact always), and for a dot with the exact product also
+    // the product's FMA remainder x*y - p.
+    constexpr bool kTrack = DOT && (M == kFast || M == kRigorous);
     constexpr bool kFastForm = (M == kFast || M == kFastRounded);
-    T p = DOT ? xv * yv : xv;
-    T t = s + p;
+    const T p = DOT ? xv * yv : xv;
+    T t, r;
     if constexpr (kFastForm) {
-      // Example 1: c = (t - s) - item is the negated round-off of s + item
-      // when |s| >= |item| (Theorem 1).
-      T c = (t - s) - p;
-      if constexpr (kTrack) {
-        T pi = fma_rn(xv, yv, -p);  // x*y - p, exact
-        e = e + (pi - c);
-      } else {
-        e = e - c;
-      }
+      fast_two_sum(s, p, t, r);
     } else {
-      // Example 3: yt and t - yt are the parts of t attributed to the item
-      // and to s; dy + ds is the exact round-off of s + item (Theorem 2).
-      T yt = t - s;
-      T dy = p - yt;
-      T ds = s - (t - yt);
-      if constexpr (kTrack) {
-        T pi = fma_rn(xv, yv, -p);
-        e = e + ((ds + dy) + pi);
-      } else {
-        e = e + (ds + dy);
-      }
+      two_sum(s, p, t, r);
+    }
+    if constexpr (kTrack) {
+      e = e + (r + fma_rn(xv, yv, -p));
+    } else {
+      e = e + r;
     }
     s = t;
   }
@@ -187,22 +179,13 @@ __device__ __forceinline__ void combine(A& s1, A& e1, A s2, A e2) {
   } else if constexpr (M == kMixed) {
     // two-sum of the binary32 values in binary32, remainder into the
     // binary64 error
-    const float a = static_cast<float>(s1), b = static_cast<float>(s2);
-    const float x = a + b;
-    const float bp = x - a;
-    const float ap = x - bp;
-    const float bh = b - bp;
-    const float ah = a - ap;
-    const float y = ah + bh;
+    float x, y;
+    two_sum(static_cast<float>(s1), static_cast<float>(s2), x, y);
     e1 = (e1 + e2) + static_cast<double>(y);
     s1 = static_cast<double>(x);
   } else {
-    A x = s1 + s2;
-    A bp = x - s1;
-    A ap = x - bp;
-    A bh = s2 - bp;
-    A ah = s1 - ap;
-    A y = ah + bh;
+    A x, y;
+    two_sum(s1, s2, x, y);
     e1 = (e1 + e2) + y;
     s1 = x;
   }
