@@ -187,7 +187,9 @@ typedef struct {
 
 /* Fill *out with the configuration a call with launch == NULL uses:
  * kind 0 single vector (n elements), 1 segmented (n total elements,
- * nseg segments). dtype 4 or 8; mode TWOFOLD_*. */
+ * nseg segments: the table's segmented rows are chosen by n and by the
+ * mean segment length n / nseg, short segments having rows of their own).
+ * dtype 4 or 8; mode TWOFOLD_*. */
 int twofold_default_launch(int kind, int dtype, int is_dot, int mode, int64_t n, int64_t nseg,
                            twofold_launch_t* out);
 

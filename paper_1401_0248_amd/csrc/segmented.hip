@@ -127,7 +127,7 @@ int seg_entry(const T* x, const T* y, int64_t n_total, const int64_t* off, int64
       !elem_aligned(out, out_f64(dtype, mode) ? 8 : 4) || !elem_aligned(off, 8))
     return TWOFOLD_EALIGN;
   twofold_launch_t lc;
-  const int rc = resolve_seg(dtype, DOT, mode, n_total, launch, &lc);
+  const int rc = resolve_seg(dtype, DOT, mode, n_total, nseg, launch, &lc);
   if (rc) return rc;
   if (nseg == 0) return TWOFOLD_OK;
   const SegLayout L = seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems));
@@ -216,7 +216,7 @@ size_t twofold_workspace_bytes_seg(int dtype, int is_dot, int mode, int64_t n_to
       !mode_ok(dtype, is_dot != 0, mode))
     return 0;
   twofold_launch_t lc;
-  if (resolve_seg(dtype, is_dot != 0, mode, n_total, launch, &lc)) return 0;
+  if (resolve_seg(dtype, is_dot != 0, mode, n_total, nseg, launch, &lc)) return 0;
   return seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems)).total;
 }
 
@@ -295,7 +295,7 @@ int twofold_seg_plan_create(const int64_t* offsets_host, int64_t nseg, int dtype
   const int64_t n_total = offsets_host[nseg];
   if (!valid_count(n_total)) return TWOFOLD_EINVAL;
   twofold_launch_t lc;
-  const int rc = resolve_seg(dtype, is_dot != 0, mode, n_total, launch, &lc);
+  const int rc = resolve_seg(dtype, is_dot != 0, mode, n_total, nseg, launch, &lc);
   if (rc) return rc;
   int64_t* tb = static_cast<int64_t*>(malloc(sizeof(int64_t) * size_t(nseg + 1)));
   if (!tb) return TWOFOLD_EINVAL;

@@ -206,7 +206,7 @@ int twofold_default_launch(int kind, int dtype, int is_dot, int mode, int64_t n,
     return TWOFOLD_EINVAL;
   if (!mode_ok(dtype, is_dot != 0, mode)) return TWOFOLD_EINVAL;
   if (kind == 0) return resolve_single(dtype, is_dot != 0, mode, n, nullptr, out);
-  return resolve_seg(dtype, is_dot != 0, mode, n, nullptr, out);
+  return resolve_seg(dtype, is_dot != 0, mode, n, nseg, nullptr, out);
 }
 
 int twofold_tuned_launch(int kind, int dtype, int is_dot, int mode, int64_t n, int64_t nseg,
@@ -214,7 +214,8 @@ int twofold_tuned_launch(int kind, int dtype, int is_dot, int mode, int64_t n, i
   const int rc = twofold_default_launch(kind, dtype, is_dot, mode, n, nseg, out);
   if (rc) return rc;
   twofold_launch_t row;
-  return lookup_rows(kind, dtype, is_dot != 0, mode, n, &row) ? TWOFOLD_OK : TWOFOLD_ENOTUNED;
+  const int64_t len = kind == 1 ? mean_len(n, nseg) : 0;
+  return lookup_rows(kind, dtype, is_dot != 0, mode, n, len, &row) ? TWOFOLD_OK : TWOFOLD_ENOTUNED;
 }
 
 size_t twofold_workspace_bytes_single(int dtype, int is_dot, int mode, int64_t n,

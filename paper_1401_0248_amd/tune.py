@@ -151,35 +151,52 @@ def tune_single(dev, quick, combos, only_buckets=None, passes=1):
             gbs = n * dtype * (2 if is_dot else 1) / t / 1e9
             log("single dtype=%d dot=%d %s n=%d: bt=%d u=%d max_blocks=%d  %.2f us  %.0f GB/s"
                 % (dtype, is_dot, MODES[mode], n, bt, u, gb, t * 1e6, gbs))
-            rows.append("{0, %d, %d, %d, %s, %d, %d, %d, 0},  // %.0f GB/s at n=%d"
+            rows.append("{0, %d, %d, %d, %s, INT64_MAX, %d, %d, %d, 0},  // %.0f GB/s at n=%d"
                         % (dtype, is_dot, mode, n_max, bt, u, gb, gbs, n))
             del xs, ys
             torch.cuda.empty_cache()
     return rows
 
 
+# Mean segment length up to which the short-segment rows apply.
+SHORT_LEN = 1024
+
+
+def seg_candidates(quick, short):
+    """(tile multiple tm, unroll, block threads, grid blocks). Short segments
+    (each one tile, latency-bound) want many waves and little unroll; the
+    tile size matters only for their rare long segments."""
+    if short:
+        if quick:
+            return itertools.product((16,), (1, 2), (256,), (1024, 2048))
+        return itertools.product((16, 64), (1, 2, 4), (256, 512), (512, 1024, 2048))
+    return itertools.product((16, 64) if quick else (16, 32, 64, 128, 256, 512),
+                             (2, 4) if quick else (2, 4, 8),
+                             (256, 512) if quick else (256, 512, 1024),
+                             (256, 1024) if quick else (256, 512, 1024))
+
+
 def tune_seg(dev, quick, combos):
     import synth
     rows = []
-    buckets = [((1 << 24), synth.segment_lengths(3, 2000, max_len=1 << 14)),
-               ((1 << 29), synth.segment_lengths(3, 20000, max_len=1 << 17)),
-               (INT64_MAX, synth.segment_lengths(3, 20000, max_len=1 << 20))]
+    # (n_max, len_max, lengths): the short-segment rows come first, so that
+    # they win for any total size when the mean length is at most SHORT_LEN
+    buckets = [(INT64_MAX, SHORT_LEN, synth.segment_lengths(5, 500000, max_len=1 << 11)),
+               ((1 << 24), INT64_MAX, synth.segment_lengths(3, 2000, max_len=1 << 14)),
+               ((1 << 29), INT64_MAX, synth.segment_lengths(3, 20000, max_len=1 << 17)),
+               (INT64_MAX, INT64_MAX, synth.segment_lengths(3, 20000, max_len=1 << 20))]
     if quick:
-        buckets = buckets[:2]
+        buckets = buckets[:3]
     for dtype, is_dot, mode in combos:
         tdt = torch.float32 if dtype == 4 else torch.float64
         W = 16 // dtype
-        for n_max, lengths in buckets:
+        for n_max, len_max, lengths in buckets:
             off = synth.offsets_from_lengths(lengths)
             n = int(off[-1])
             x = torch.empty(n, dtype=tdt, device=dev).uniform_(-1, 1)
             y = torch.empty(n, dtype=tdt, device=dev).uniform_(-1, 1) if is_dot else None
             best = None
-            cands = itertools.product((16, 64) if quick else (16, 32, 64, 128, 256, 512),
-                                      (2, 4) if quick else (2, 4, 8),
-                                      (256, 512) if quick else (256, 512, 1024),
-                                      (256, 1024) if quick else (256, 512, 1024))
-            for tm, u, bt, gb in cands:
+            for tm, u, bt, gb in seg_candidates(quick, len_max != INT64_MAX):
                 if spills(bt, u, is_dot):
                     continue
                 lc = tf.Launch(bt, u, gb, 0, 64 * W * tm)
@@ -199,17 +216,19 @@ def tune_seg(dev, quick, combos):
             gbs = n * dtype * (2 if is_dot else 1) / t / 1e9
             log("seg dtype=%d dot=%d %s n=%d nseg=%d: bt=%d u=%d grid=%d tile=%d  %.1f us  %.0f GB/s"
                 % (dtype, is_dot, MODES[mode], n, len(lengths), bt, u, gb, ts, t * 1e6, gbs))
-            rows.append("{1, %d, %d, %d, %s, %d, %d, %d, %d},  // %.0f GB/s at n=%d, %d segments"
-                        % (dtype, is_dot, mode, n_max, bt, u, gb, ts, gbs, n, len(lengths)))
+            rows.append("{1, %d, %d, %d, %s, %s, %d, %d, %d, %d},  // %.0f GB/s at n=%d, %d segments"
+                        % (dtype, is_dot, mode, n_max, len_max, bt, u, gb, ts, gbs, n,
+                           len(lengths)))
             del x, y
             torch.cuda.empty_cache()
     return rows
 
 
-HEADER = """// Tuned launch table: {kind, dtype, is_dot, mode, n_max, block_threads,
-// unroll, max_blocks, tile_elems}. kind 0 single vector, 1 segmented.
-// Rows are searched in order; the first row whose n_max is at least the
-// call's n (segmented: total elements) wins. Single-vector rows give the
+HEADER = """// Tuned launch table: {kind, dtype, is_dot, mode, n_max, len_max,
+// block_threads, unroll, max_blocks, tile_elems}. kind 0 single vector, 1
+// segmented. Rows are searched in order; the first row whose n_max is at
+// least the call's n (segmented: total elements) and whose len_max is at
+// least its mean segment length wins. Single-vector rows give the
 // largest grid: a call uses the blocks one round needs, at most max_blocks.
 // Written by paper_1401_0248_amd/tune.py on %s; the comments give the
 // throughput measured for the row's timed size.

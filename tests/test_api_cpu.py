@@ -386,6 +386,46 @@ def test_tuned_launch_reports_measured_rows():
     assert L.twofold_tuned_launch(0, 4, 0, 0, 10, 0, None) == EINVAL
 
 
+def _seg_rows():
+    """Segmented rows of the launch table, parsed from its source:
+    (dtype, is_dot, mode, n_max, len_max) -> (block, unroll, grid, tile)."""
+    import re
+    path = os.path.join(os.path.dirname(_lib.__file__), "csrc", "tuned_table.inc")
+    big = 2 ** 63 - 1
+    rows = []
+    for line in open(path):
+        m = re.match(r"\{1, (\d+), (\d+), (\d+), (\w+), (\w+), (\d+), (\d+), (\d+), (\d+)\}", line)
+        if m:
+            v = [big if g == "INT64_MAX" else int(g) for g in m.groups()]
+            rows.append((tuple(v[:5]), tuple(v[5:])))
+    return rows
+
+
+def test_short_segments_take_their_own_rows():
+    """Every segmented form has a row for short segments (mean length at
+    most 1024 elements, any total size), searched first: a batch of short
+    segments gets it, one with longer segments the size rows."""
+    import paper_1401_0248_amd as tf
+    rows = _seg_rows()
+    for dt in (4, 8):
+        for dot in (0, 1):
+            for mode in range(8):
+                if (mode in (5, 6) and not dot) or (mode == 7 and dt == 8):
+                    continue
+                mine = [r for r in rows if r[0][:3] == (dt, dot, mode)]
+                short = [r for r in mine if r[0][4] == 1024]
+                assert len(short) == 1 and mine[0] == short[0], (dt, dot, mode)
+                want = short[0][1]
+                n = 1 << 27
+                for nseg in (n // 16, n // 1024):  # mean 16 and 1024 elements
+                    lc, measured = tf.tuned_launch(1, dt, dot, mode, n, nseg)
+                    assert measured
+                    assert (lc.block_threads, lc.unroll, lc.grid_blocks, lc.tile_elems) == want
+                lc = tf.default_launch(1, dt, dot, mode, n, n // 1025)  # mean 1025
+                size_rows = [r for r in mine if r[0][4] != 1024 and n <= r[0][3]]
+                assert (lc.block_threads, lc.unroll, lc.grid_blocks, lc.tile_elems) == size_rows[0][1]
+
+
 def test_batch_item_reserved_must_be_zero():
     from paper_1401_0248_amd._lib import BatchItem
     L = _lib.load()
