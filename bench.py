@@ -778,17 +778,22 @@ def roofline_sweep(np, torch, tf, dev):
 
 def segmented_batch(np, torch, tf, dev):
     """20,000 segment pairs with log-uniform lengths in [1, 2^20] (seed 3,
-    1,504,333,896 elements), and the secondary variant capped at 2^17
-    (221,217,512 elements); uniform(-1, 1) data of seed 3 (x, then y),
-    binary32 and binary64, fast and rigorous dots through plans with the
-    tuned default launch, HIP-graph replay, plus the precision monitor over
-    the rigorous results. One JSON line."""
+    1,504,333,896 elements), the secondary variant capped at 2^17
+    (221,217,512 elements), and a batch of short segments (1,000,000
+    log-uniform in [1, 2^9], seed 9: the launch rows for short segments);
+    uniform(-1, 1) data of seed 3 (x, then y), binary32 and binary64, fast
+    and rigorous dots through plans with the tuned default launch,
+    HIP-graph replay, plus the precision monitor over the rigorous results.
+    One JSON line."""
     import synth
 
     rows = []
     for dtype, tdt in ((np.float32, torch.float32), (np.float64, torch.float64)):
-        for cap in (1 << 20, 1 << 17):
-            lengths = synth.segment_lengths(3, 20000, max_len=cap)
+        for cap in (1 << 20, 1 << 17, 1 << 9):
+            if cap == 1 << 9:
+                lengths = synth.segment_lengths(9, 1000000, max_len=cap)
+            else:
+                lengths = synth.segment_lengths(3, 20000, max_len=cap)
             off = synth.offsets_from_lengths(lengths)
             n = int(off[-1])
             log("segmented %s, lengths up to 2^%d: generating %d x 2 values"
@@ -826,7 +831,8 @@ def segmented_batch(np, torch, tf, dev):
             del both, x, y
             torch.cuda.empty_cache()
     print(json.dumps({"workload": "segmented twofold dot, 20,000 log-uniform segments in "
-                                  "[1, 2^20] (and the 2^17-capped variant), seed 3",
+                                  "[1, 2^20] (and the 2^17-capped variant), seed 3; "
+                                  "1,000,000 short segments in [1, 2^9], seed 9",
                       "peak_gb_s": HBM_PEAK_GBS, "device": device_info(torch, dev),
                       "rows": rows}), flush=True)
 
