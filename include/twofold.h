@@ -123,9 +123,10 @@
  * the same time need separate workspaces. A single-vector call that runs
  * one block does not touch ws (it may then be NULL).
  * Kernels: a single-vector, multi-vector or batch call is one kernel (one
- * block) or two (blocks, then the binary64 combine); a segmented call is the
- * tiling kernel (device offsets only), the tile kernel and the per-segment
- * combine kernel. Later kernels see earlier ones' results through the
+ * block) or two (blocks, then the binary64 combine); a segmented call is
+ * three small tiling kernels (device offsets only: per-row tile counts, the
+ * rows' prefix, then the tile and wave tables), the tile kernel and the
+ * per-segment combine kernel. Later kernels see earlier ones' results through the
  * stream order alone: no kernel waits on, or fences for, another block.
  * Status: 0 on success, a negative TWOFOLD_E* code otherwise; arguments are
  * checked on the host before any HIP call, and nothing is launched on

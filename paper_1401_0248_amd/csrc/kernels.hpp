@@ -468,10 +468,13 @@ __device__ __forceinline__ void tile_store(A s, A e, int lane, int64_t t, int64_
 }
 
 // The tiles [t0, t1) of one wave with loads one round ahead of the steps,
-// across tile boundaries too: while a tile's last (partial) round, tail and
-// combine run, the next tile's head, tail and first round are in flight.
-// Per tile, the steps are those of lane_reduce with L = 64, in the same
-// order, so every pair is the same.
+// across tile boundaries too: the next tile's head, tail and first round
+// are requested before the current tile's last (partial) round, tail and
+// combine. (The compiler waits for them where they move into the round
+// buffers at the next tile's start, so at a tile boundary no other load is
+// in flight; a variant without that move was no faster.) Per tile, the
+// steps are those of lane_reduce with L = 64, in the same order, so every
+// pair is the same.
 template <typename T, typename A, int M, bool DOT, bool YV, int U>
 __device__ __forceinline__ void seg_tiles_ahead(const T* __restrict__ x, const T* __restrict__ y,
                                                 SegWalk& wk, int64_t t0, int64_t t1, int lane,

@@ -18,42 +18,131 @@ using namespace twofold::host;
 
 namespace {
 
-// Tile table from device offsets (one block of 1024 threads), rows of 1024
-// segments: tiles per segment, block-wide exclusive scan, running carry.
-// Also records in *status whether the offsets are valid (offsets[0] >= 0,
-// non-decreasing, offsets[nseg] <= n_total).
-__global__ void __launch_bounds__(1024)
-seg_tiles_kernel(const int64_t* __restrict__ off, int64_t nseg, int64_t n_total, int64_t TS,
-                 int64_t* __restrict__ tbase, uint32_t* __restrict__ status) {
-  __shared__ int64_t sh[1024];
-  __shared__ int sh_bad;
+// Tile table and wave table from device offsets, in three kernels over
+// rows of kSegRow segments (one block of kSegRow threads a row; the grids
+// stride over rows).
+//
+// 1. Each segment's tiles, their exclusive scan within the row (in LDS,
+//    into tbase), the row's total into rows[r] and whether the row's
+//    offsets are invalid into bad[r] (offsets[0] >= 0, non-decreasing,
+//    offsets[nseg] <= n_total).
+__global__ void __launch_bounds__(kSegRow)
+seg_count_kernel(const int64_t* __restrict__ off, int64_t nseg, int64_t n_total, int64_t TS,
+                 int64_t* __restrict__ tbase, int64_t* __restrict__ rows,
+                 uint32_t* __restrict__ bad) {
+  __shared__ int64_t sh[kSegRow];
   const int t = threadIdx.x;
-  if (t == 0) sh_bad = (off[0] < 0 || off[nseg] > n_total) ? 1 : 0;
-  __syncthreads();
-  int64_t carry = 0;
-  for (int64_t base = 0; base < nseg; base += 1024) {
-    const int64_t sg = base + t;
+  const int64_t nrow = (nseg + kSegRow - 1) / kSegRow;
+  for (int64_t r = blockIdx.x; r < nrow; r += gridDim.x) {
+    const int64_t sg = r * kSegRow + t;
     int64_t tiles = 0;
+    int b = 0;
     if (sg < nseg) {
       const int64_t len = off[sg + 1] - off[sg];
-      if (len < 0) sh_bad = 1;  // benign race: every writer stores 1
+      b = len < 0;
       tiles = len > 0 ? (len + TS - 1) / TS : 0;
     }
+    if (r == 0 && t == 0 && (off[0] < 0 || off[nseg] > n_total)) b = 1;
     sh[t] = tiles;
     __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+    for (int d = 1; d < kSegRow; d <<= 1) {  // inclusive Hillis-Steele scan
       const int64_t v = t >= d ? sh[t - d] : 0;
       __syncthreads();
       sh[t] += v;
       __syncthreads();
     }
-    if (sg < nseg) tbase[sg] = carry + sh[t] - tiles;
-    carry += sh[1023];
+    if (sg < nseg) tbase[sg] = sh[t] - tiles;
+    const int any = __syncthreads_or(b);
+    if (t == 0) {
+      rows[r] = sh[kSegRow - 1];
+      bad[r] = any ? 1u : 0u;
+    }
+    __syncthreads();  // sh is reused by the next row
+  }
+}
+
+// 2. (one block) The rows' totals become their exclusive prefix sums,
+//    rows[nrow] the number of tiles, and *status whether any row is invalid.
+__global__ void __launch_bounds__(kSegRow)
+seg_rows_kernel(int64_t nrow, int64_t* __restrict__ rows, const uint32_t* __restrict__ bad,
+                uint32_t* __restrict__ status) {
+  __shared__ int64_t sh[kSegRow];
+  const int t = threadIdx.x;
+  int64_t carry = 0;
+  int b = 0;
+  for (int64_t base = 0; base < nrow; base += kSegRow) {
+    const int64_t r = base + t;
+    const int64_t v = r < nrow ? rows[r] : 0;
+    if (r < nrow && bad[r]) b = 1;
+    sh[t] = v;
+    __syncthreads();
+    for (int d = 1; d < kSegRow; d <<= 1) {
+      const int64_t u = t >= d ? sh[t - d] : 0;
+      __syncthreads();
+      sh[t] += u;
+      __syncthreads();
+    }
+    if (r < nrow) rows[r] = carry + sh[t] - v;
+    carry += sh[kSegRow - 1];
     __syncthreads();
   }
+  const int any = __syncthreads_or(b);
   if (t == 0) {
-    tbase[nseg] = carry;
-    *status = sh_bad ? 1u : 0u;
+    rows[nrow] = carry;
+    *status = any ? 1u : 0u;
+  }
+}
+
+// 3. Each segment's tile base gets its row's prefix, tbase[nseg] the number
+//    of tiles; with valid offsets, the wave table of the launch (nw waves;
+//    the cost model and meaning of a plan's, build_wave_table): segment s
+//    covers the start costs [cbase(s), cbase(s + 1)) and writes the entries
+//    of the waves w < nw whose bound floor(w*C/nw) falls there. With no
+//    tiles at all every wave gets the empty range.
+__global__ void __launch_bounds__(kSegRow)
+seg_finish_kernel(const int64_t* __restrict__ off, int64_t nseg, int64_t TS, int64_t c0,
+                  int64_t* __restrict__ tbase, const int64_t* __restrict__ rows,
+                  const uint32_t* __restrict__ status, int64_t nw, int64_t* __restrict__ wtab) {
+  const int t = threadIdx.x;
+  const int64_t nrow = (nseg + kSegRow - 1) / kSegRow;
+  const int64_t NT = rows[nrow];
+  const bool table = wtab && *status == 0;
+  const int64_t o0 = off[0];
+  const int64_t C = table ? (off[nseg] - o0) + c0 * NT : 0;
+  if (blockIdx.x == 0 && t == 0) {
+    tbase[nseg] = NT;
+    if (table) {
+      wtab[2 * nw] = NT;
+      wtab[2 * nw + 1] = nseg - 1;
+    }
+  }
+  if (table && C == 0) {
+    for (int64_t w = int64_t(blockIdx.x) * kSegRow + t; w < nw; w += int64_t(gridDim.x) * kSegRow) {
+      wtab[2 * w] = 0;
+      wtab[2 * w + 1] = 0;
+    }
+  }
+  for (int64_t r = blockIdx.x; r < nrow; r += gridDim.x) {
+    const int64_t sg = r * kSegRow + t;
+    if (sg >= nseg) continue;
+    const int64_t tb = tbase[sg] + rows[r];
+    tbase[sg] = tb;
+    if (!table || C == 0) continue;
+    const int64_t len = off[sg + 1] - off[sg];
+    const int64_t ntl = len > 0 ? (len + TS - 1) / TS : 0;
+    const int64_t a = (off[sg] - o0) + c0 * tb;  // cbase(sg)
+    const int64_t b = a + len + c0 * ntl;         // cbase(sg + 1)
+    // the waves with a <= floor(w*C/nw) < b: w in [ceil(a*nw/C), ceil(b*nw/C))
+    auto ceil_w = [&](int64_t c) {
+      return static_cast<int64_t>((static_cast<__int128>(c) * nw + (C - 1)) / C);
+    };
+    const int64_t we = ceil_w(b) < nw ? ceil_w(b) : nw;
+    for (int64_t w = ceil_w(a); w < we; w++) {
+      const int64_t lo = static_cast<int64_t>((static_cast<__int128>(w) * C) / nw);
+      const int64_t i = ((lo - a) + TS + c0 - 1) / (TS + c0);
+      wtab[2 * w] = i < ntl ? tb + i : tb + ntl;
+      wtab[2 * w + 1] = sg;
+    }
   }
 }
 
@@ -130,17 +219,28 @@ int seg_entry(const T* x, const T* y, int64_t n_total, const int64_t* off, int64
   const int rc = resolve_seg(dtype, DOT, mode, n_total, nseg, launch, &lc);
   if (rc) return rc;
   if (nseg == 0) return TWOFOLD_OK;
-  const SegLayout L = seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems));
+  const int64_t nw = int64_t(lc.grid_blocks) * (lc.block_threads / 64);
+  const SegLayout L = seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems), nw);
   if (!ws_ok(ws, ws_bytes, L.total)) return TWOFOLD_EWORKSPACE;
   char* base = static_cast<char*>(ws);
   uint32_t* status = reinterpret_cast<uint32_t*>(base);
   int64_t* tbase = reinterpret_cast<int64_t*>(base + L.tbase_off);
   double* slots = reinterpret_cast<double*>(base + L.slots_off);
+  int64_t* rows = reinterpret_cast<int64_t*>(base + L.rows_off);
+  uint32_t* bad = reinterpret_cast<uint32_t*>(base + L.bad_off);
+  int64_t* wtab = nw <= kMaxSeqWaves ? reinterpret_cast<int64_t*>(base + L.wtab_off) : nullptr;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int rc2 = launch_kernel(seg_tiles_kernel, dim3(1), dim3(1024), st, off, nseg, n_total,
-                                lc.tile_elems, tbase, status);
+  const int64_t nrow = seg_rows(nseg);
+  const dim3 grid(static_cast<unsigned>(nrow < kSegRowGrid ? nrow : kSegRowGrid));
+  const dim3 block(static_cast<unsigned>(kSegRow));
+  int rc2 = launch_kernel(seg_count_kernel, grid, block, st, off, nseg, n_total, lc.tile_elems,
+                          tbase, rows, bad);
+  if (!rc2) rc2 = launch_kernel(seg_rows_kernel, dim3(1), block, st, nrow, rows, bad, status);
+  if (!rc2)
+    rc2 = launch_kernel(seg_finish_kernel, grid, block, st, off, nseg, lc.tile_elems,
+                        seg_tile_cost(dtype, DOT), tbase, rows, status, nw, wtab);
   if (rc2) return rc2;
-  return seg_by_mode<T, DOT>(mode, x, y, off, nseg, tbase, nullptr, status, lc, slots, out, st);
+  return seg_by_mode<T, DOT>(mode, x, y, off, nseg, tbase, wtab, status, lc, slots, out, st);
 }
 
 // Plans with at most this many waves carry a wave table (16 bytes a wave).
@@ -217,7 +317,9 @@ size_t twofold_workspace_bytes_seg(int dtype, int is_dot, int mode, int64_t n_to
     return 0;
   twofold_launch_t lc;
   if (resolve_seg(dtype, is_dot != 0, mode, n_total, nseg, launch, &lc)) return 0;
-  return seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems)).total;
+  return seg_layout(nseg, seg_max_tiles(n_total, nseg, lc.tile_elems),
+                    int64_t(lc.grid_blocks) * (lc.block_threads / 64))
+      .total;
 }
 
 int twofold_segsum_f32(const float* x, int64_t n_total, const int64_t* offsets, int64_t nseg,
