@@ -246,3 +246,74 @@ def test_many_tiny_segments():
     want = np.zeros(L.size)
     want[L == 1] = x
     assert np.array_equal(got[:, 0], want) and np.all(got[:, 1] == 0)
+
+
+def _ragged_offsets(seed, nseg, max_len):
+    rng = np.random.default_rng(seed)
+    L = rng.integers(0, max_len + 1, nseg).astype(np.int64)
+    L[rng.random(nseg) < 0.2] = 0
+    return synth.offsets_from_lengths(L)
+
+
+@pytest.mark.parametrize("nseg", [1023, 1024, 1025, 3073])
+def test_device_offsets_across_rows_vs_model(nseg):
+    """Segment counts around the tiling kernels' rows of 1024 segments, at a
+    launch with a wave table and at one with more than 2^20 waves (no wave
+    table: the tile kernel finds its bounds by search). Device-offset calls
+    and plans, bitwise against the order model."""
+    W = 4
+    off = _ragged_offsets(nseg, nseg, 300)
+    x = synth.uniform(nseg + 1, int(off[-1]), np.float32)
+    xd, mis = to_dev(x, 1)
+    od = torch.from_numpy(off).to(DEV)
+    for bt, u, gb, ts in ((256, 2, 64, 64 * W * 2), (128, 1, (1 << 19) + 8, 64 * W)):
+        lc = launch(bt, u, gb, ts)
+        want = oracle.model_seg("rigorous", x, off, None, mis, u, ts)
+        gt = tf.segsum(xd, od, "rigorous", lc)
+        got = _rows(gt)
+        bad = [s for s in range(nseg) if not same_bits(got[s], want[s])]
+        assert not bad, (nseg, gb, bad[:5])
+        plan = tf.SegPlan(off, xd.dtype, False, "rigorous", lc)
+        assert torch.equal(plan.execute(xd).view(torch.int32), gt.view(torch.int32))
+        plan.close()
+
+
+def test_invalid_device_offsets_in_a_later_row():
+    """An offset that decreases in the fourth row of 1024 segments, or a last
+    offset past the data, makes every segment NaN; the same workspace then
+    serves a valid call."""
+    nseg = 5000
+    off = _ragged_offsets(11, nseg, 40)
+    x = torch.ones(int(off[-1]), dtype=torch.float32, device=DEV)
+    ws = tf.Workspace(1 << 24, DEV)
+    for s, delta in ((3500, -(int(off[3500] - off[3499]) + 1)), (nseg, 1)):
+        bad = off.copy()
+        bad[s] += delta
+        assert bad[s] < bad[s - 1] or bad[-1] > off[-1]
+        out = _rows(tf.segsum(x, torch.from_numpy(bad).to(DEV), "rigorous", ws=ws))
+        assert np.all(np.isnan(out)), s
+    out = _rows(tf.segsum(x, torch.from_numpy(off).to(DEV), "rigorous", ws=ws))
+    assert np.array_equal(out[:, 0], np.diff(off).astype(np.float64)) and np.all(out[:, 1] == 0)
+
+
+def test_more_rows_than_the_row_grid():
+    """65,536 x 1024 + 1500 segments of 0, 1 or 2 small integers: the tiling
+    kernels stride over more rows than they launch blocks, and the combine
+    kernel over more segments than its grid. Every sum is exact."""
+    nseg = 65536 * 1024 + 1500
+    rng = np.random.default_rng(12)
+    L = rng.integers(0, 3, nseg).astype(np.int64)
+    off = synth.offsets_from_lengths(L)
+    del L
+    n = int(off[-1])
+    xi = rng.integers(-8, 9, n).astype(np.int64)
+    cs = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(xi, out=cs[1:])
+    want = (cs[off[1:]] - cs[off[:-1]]).astype(np.float64)
+    del cs
+    xd = torch.from_numpy(xi.astype(np.float32)).to(DEV)
+    del xi
+    od = torch.from_numpy(off).to(DEV)
+    got = tf.segsum(xd, od, "rigorous").cpu().numpy().astype(np.float64)
+    assert np.array_equal(got[:, 0], want)
+    assert np.all(got[:, 1] == 0)
