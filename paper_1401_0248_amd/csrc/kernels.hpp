@@ -113,6 +113,18 @@ __device__ __forceinline__ int64_t head_count(const T* p, int64_t len) {
   return h < len ? h : len;
 }
 
+// v, hidden from the compiler's uniformity analysis. A head element is
+// loaded by the lanes below the head count, which for binary64 data is at
+// most 1: the compiler then proves the address uniform and makes the load a
+// scalar one, waited for at once inside its branch, so the loads after it
+// (tail, first round) wait a whole memory round trip before they are even
+// issued. Indexed through this value it stays a vector load, waited for
+// with the rest.
+__device__ __forceinline__ int64_t opaque_lane(int64_t v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
 // Steps 1-4 of the documented order for one lane g of L lanes over the
 // range [x, x + len): head, rounds of U vectors, tail, chain merge.
 //
@@ -140,12 +152,13 @@ __device__ __forceinline__ void lane_reduce(const T* __restrict__ x, const T* __
   const T* __restrict__ yb = DOT ? y + head : nullptr;
   const int64_t nv = (len - head) / W;
   const int64_t tail0 = nv * W;
-  const bool has_head = g < head;
+  const int64_t gh = opaque_lane(g);
+  const bool has_head = gh < head;
   const bool has_tail = g < (len - head) - tail0;
   T hx = T(0), hy = T(0), tx = T(0), ty = T(0);
   if (has_head) {
-    hx = load_nt(x + g);
-    if constexpr (DOT) hy = load_nt(y + g);
+    hx = load_nt(x + gh);
+    if constexpr (DOT) hy = load_nt(y + gh);
   }
   if (has_tail) {
     tx = load_nt(xb + tail0 + g);
@@ -414,7 +427,7 @@ struct SegWalk {
   int64_t tb = 0, tend = 0, oa = 0, ob = 0, nx_tend = 0, nx_ob = 0;
 
   __device__ __forceinline__ void prefetch() {
-    if (sg + 1 < nseg) {
+    if (sg + 1 != nseg) {  // sg < nseg
       nx_tend = tbase[sg + 2];
       nx_ob = off[sg + 2];
     }
@@ -428,15 +441,16 @@ struct SegWalk {
     ob = off[sg + 1];
     prefetch();
   }
-  // Move on to tile t, at or after the current one.
+  // Move on to tile t: the current one or the next (t <= tend, so the
+  // tests are equalities, which the scalar unit does on 64 bits).
   __device__ __forceinline__ void to(int64_t t) {
-    if (t < tend) return;
+    if (t != tend) return;
     sg++;
     tb = tend;
     oa = ob;
     tend = nx_tend;
     ob = nx_ob;
-    while (tend <= t) {  // empty segments in between
+    while (tend == t) {  // empty segments in between
       sg++;
       tb = tend;
       oa = ob;
@@ -484,16 +498,25 @@ __device__ __forceinline__ void seg_tiles_ahead(const T* __restrict__ x, const T
   using V = typename vec16<T>::type;
   // The geometry of a tile [a, a + len): head elements, body vectors, full
   // rounds (uniform across the wave).
+  // A tile holds at most TS <= 2^30 elements, so everything but its start
+  // is 32-bit: the tests on it are scalar compares. (A 64-bit ordered
+  // compare of scalars goes through a vector register, which the compiler
+  // may take from a round buffer with loads in flight and wait for them.)
   struct Geo {
-    int64_t a, len, head, nv, full;
+    int64_t a;
+    int32_t len, head, nv, full;
   };
   auto geo = [&](int64_t t) {
     Geo g;
     g.a = wk.begin(t);
-    g.len = wk.end(t) - g.a;
-    g.head = head_count(x + g.a, g.len);
+    // every tile of a segment but its last holds TS elements
+    g.len = (t + 1 != wk.tend) ? static_cast<int32_t>(wk.TS) : static_cast<int32_t>(wk.ob - g.a);
+    const int32_t mis = static_cast<int32_t>(reinterpret_cast<uintptr_t>(x + g.a) & 15u) /
+                        static_cast<int32_t>(sizeof(T));
+    const int32_t h = (W - mis) % W;
+    g.head = h < g.len ? h : g.len;
     g.nv = (g.len - g.head) / W;
-    g.full = g.nv / PR;
+    g.full = g.nv / static_cast<int32_t>(PR);
     return g;
   };
   // A tile's first loads: head and tail elements, then round 0 (or, with no
@@ -503,13 +526,14 @@ __device__ __forceinline__ void seg_tiles_ahead(const T* __restrict__ x, const T
     const T* ya = DOT ? y + g.a : nullptr;
     const T* xb = xa + g.head;
     const T* yb = DOT ? ya + g.head : nullptr;
-    const int64_t tail0 = g.nv * W;
+    const int64_t tail0 = static_cast<int64_t>(g.nv) * W;
     hx = hy = tx = ty = T(0);
-    if (lane < g.head) {
-      hx = load_nt(xa + lane);
-      if constexpr (DOT) hy = load_nt(ya + lane);
+    const int64_t hl = opaque_lane(lane);
+    if (hl < g.head) {
+      hx = load_nt(xa + hl);
+      if constexpr (DOT) hy = load_nt(ya + hl);
     }
-    if (lane < (g.len - g.head) - tail0) {
+    if (lane < (g.len - g.head) - g.nv * W) {
       tx = load_nt(xb + tail0 + lane);
       if constexpr (DOT) ty = load_nt(yb + tail0 + lane);
     }
@@ -526,7 +550,8 @@ __device__ __forceinline__ void seg_tiles_ahead(const T* __restrict__ x, const T
   V va[U], vb[U];
   T hx, hy, tx, ty;
   first_loads(g, va, vb, hx, hy, tx, ty);
-  for (int64_t t = t0; t < t1; t++) {
+  // (t0 < t1; tests of tile indices as equalities, see SegWalk::to)
+  for (int64_t t = t0; t != t1; t++) {
     const int64_t sg = wk.sg, ntl = wk.tend - wk.tb;
     const T* xb = x + g.a + g.head;
     const T* yb = DOT ? y + g.a + g.head : nullptr;
@@ -562,7 +587,7 @@ __device__ __forceinline__ void seg_tiles_ahead(const T* __restrict__ x, const T
     };
     // (only whole rounds inside the loop, so its loads carry no condition
     // and the waits count exactly)
-    int64_t q = 0;
+    int32_t q = 0;
     for (; q + 2 < g.full; q += 2) {  // va holds full round q; rounds q + 1, q + 2 are full
       load_into(na, nb, k0 + PR, true);
       step_full(va, vb);
@@ -592,7 +617,7 @@ __device__ __forceinline__ void seg_tiles_ahead(const T* __restrict__ x, const T
     Geo gn = g;
     V wa[U], wb[U];
     T nhx = T(0), nhy = T(0), ntx = T(0), nty = T(0);
-    if (t + 1 < t1) {
+    if (t + 1 != t1) {
       wk.to(t + 1);
       gn = geo(t + 1);
       first_loads(gn, wa, wb, nhx, nhy, ntx, nty);

@@ -34,8 +34,8 @@ N_ILL = 1 << 24
 BENCH_TABLE = {(8, 1, "rigorous"): (256, 2, 256), (8, 1, "fast"): (256, 4, 256),
                (4, 1, "rigorous"): (256, 2, 256), (4, 1, "fast"): (512, 1, 256)}
 # segmented dots above 2^29 elements: (block_threads, unroll, grid, tile)
-SEG_TABLE = {(4, "rigorous"): (256, 2, 256, 16384), (4, "fast"): (256, 2, 256, 16384),
-             (8, "rigorous"): (256, 2, 256, 32768), (8, "fast"): (256, 2, 256, 32768)}
+SEG_TABLE = {(4, "rigorous"): (256, 2, 256, 16384), (4, "fast"): (256, 2, 256, 32768),
+             (8, "rigorous"): (256, 2, 256, 32768), (8, "fast"): (256, 2, 256, 16384)}
 
 
 def _u(dtype):
@@ -261,7 +261,7 @@ def test_segmented_full_batch_sampled(dtype):
 # binary32 sums above 2^31 elements: (block_threads, unroll, max_blocks) and
 # the segmented (unroll, tile) of the tuned table, restated like the others
 BIG_SUM = (256, 4, 256)
-BIG_SEG_SUM = (4, 32768)
+BIG_SEG_SUM = (8, 32768)
 
 
 def test_beyond_2e31_elements():
