@@ -140,6 +140,16 @@ def test_segmented_argument_checks():
     assert L.twofold_segdot_f64(fake, fake, 1 << 20, fake, 5000, 2, None, fake, ws, 1024, None) == EWORKSPACE
     lc = Launch(256, 4, 16, 0, 1000)  # tile not a multiple of 64*W
     assert L.twofold_segsum_f32(fake, 10, fake, 3, 2, ctypes.byref(lc), fake, ws, 1 << 20, None) == EINVAL
+    # a tile holds at most 2^30 elements (the tile kernel keeps a tile's
+    # geometry in 32 bits), on both segmented paths
+    big_tile = Launch(256, 4, 16, 0, (1 << 30) + 256)
+    assert L.twofold_segsum_f32(fake, 10, fake, 3, 2, ctypes.byref(big_tile), fake, ws, 1 << 20,
+                                None) == EINVAL
+    offs = np.array([0, 4, 8, 10], dtype=np.int64)
+    h = ctypes.c_void_p()
+    assert L.twofold_seg_plan_create(offs.ctypes.data_as(ctypes.c_void_p), 3, 4, 0, 2,
+                                     ctypes.byref(big_tile), ctypes.byref(h)) == EINVAL
+    assert not h.value
     # nseg == 0: nothing to do, nothing launched
     assert L.twofold_segsum_f32(fake, 0, fake, 0, 2, None, fake, ws, 1 << 20, None) == 0
     # binary64 rows of binary32 data: their own calls, checked the same way
