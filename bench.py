@@ -45,6 +45,7 @@ SEG_SEED = 3
 SEG_FORMS = (("float64", "rigorous"), ("float64", "fast"), ("float32", "rigorous"),
              ("float32", "fast"))
 ORACLE_SAMPLE_S = 25.0  # bound on the sequential oracle's timed sample
+XACC_SAMPLE_S = 3.0  # seconds of one-thread exact accumulation in the accuracy leg
 MODEL_SAMPLES = 48      # segments checked bit for bit against the order model
 
 ILLCOND_N = 1 << 24
@@ -275,9 +276,22 @@ def seg_oracle_leg(np, torch, state):
                                                              "; ".join(forms_done), done_elems, dt_s),
             "host": host_info()}
 
-    # (2) every segment of every form against the exact accumulator
-    t0 = time.perf_counter()
+    # (2) the exact accumulator alone, on one host thread, over the first
+    # binary64 segments (a bounded sample), for its rate beside the
+    # all-thread grading below
     lens = np.diff(off)
+    x64, y64 = xs["float64"]
+    t1 = time.perf_counter()
+    one_elems, one_segs = 0, 0
+    while one_segs < nseg and time.perf_counter() - t1 < XACC_SAMPLE_S:
+        a, b = int(off[one_segs]), int(off[one_segs + 1])
+        oracle.Exact(x64[a:b], y64[a:b], nthreads=1)
+        one_elems += b - a
+        one_segs += 1
+    one_s = time.perf_counter() - t1
+
+    # (3) every segment of every form against the exact accumulator
+    t0 = time.perf_counter()
 
     def exact_seg(args):
         name, s = args
@@ -307,7 +321,15 @@ def seg_oracle_leg(np, torch, state):
                       "over 4 L u^2 sum|x y| (L the segment's length) and over the proven bound "
                       "of the segment's reduction tree at the timed launch, segments above "
                       "4 L u^2 sum|x y|; value_median: median |v - S| / sum|x y|",
-           "segments_graded": nseg, "grading_s": round(grade_s, 1)}
+           "segments_graded": nseg, "grading_s": round(grade_s, 1),
+           "exact_accumulator": {
+               "all_threads_gelem_s": round(sum(len(v[0]) for v in xs.values()) / grade_s / 1e9, 4),
+               "threads": worker_threads(),
+               "one_thread_gelem_s": round(one_elems / one_s / 1e9, 4) if one_s > 0 else None,
+               "one_thread_sample": "the first %d binary64 segments, %d dot elements, in %.2f s"
+                                    % (one_segs, one_elems, one_s),
+               "note": "all threads: every segment of both types, diffs against every execute "
+                       "included"}}
     for i, e in enumerate(execs):
         dt = np.float64 if e["name"] == "float64" else np.float32
         u = bounds.unit_roundoff(dt)
