@@ -35,7 +35,7 @@ BENCH_TABLE = {(8, 1, "rigorous"): (256, 2, 256), (8, 1, "fast"): (256, 4, 256),
                (4, 1, "rigorous"): (256, 2, 256), (4, 1, "fast"): (512, 1, 256)}
 # segmented dots above 2^29 elements: (block_threads, unroll, grid, tile)
 SEG_TABLE = {(4, "rigorous"): (256, 2, 256, 16384), (4, "fast"): (256, 2, 256, 32768),
-             (8, "rigorous"): (256, 2, 256, 32768), (8, "fast"): (256, 2, 256, 16384)}
+             (8, "rigorous"): (256, 8, 256, 32768), (8, "fast"): (256, 8, 256, 32768)}
 
 
 def _u(dtype):
